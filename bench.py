@@ -1,0 +1,216 @@
+"""Benchmark: memory-efficient INR gradient steps per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
+                    [--v-mode full|at_i] [--mlp-dtype bf16|fp32] [--no-cpu]
+
+One step is one pass of the whole hot path (Algorithm 1 + Adam) on the
+501^3, 20-view, 768^2-detector cone-beam workload: grid evaluation of the
+FFN INR (3 -> 512 Fourier features + 5 x 256 ReLU -> 1) on all 98,775,657
+FOV voxels, Joseph projection, LS residual, matched adjoint, 1% index
+sample, subsampled VJP, Adam.  Inputs are seeded synthetic data
+(random-ellipsoid phantom, closed-form chord data, Poisson noise at 1e5
+photons) resident on the GPU before timing starts.
+
+Prints one JSON line with the throughput, a roofline entry for the dominant
+kernel (the grid-evaluation GEMM chain, timed with HIP events on its own
+stream) and the FP64 oracle timed on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}   # dense MFMA FLOP/s, MI355X
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c4")
+    ap.add_argument("--v-mode", default="full", choices=["full", "at_i"])
+    ap.add_argument("--mlp-dtype", default=None, choices=[None, "bf16", "fp32"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(p, target_s):
+    """The FP64 oracle on a bounded sample of one step, scaled to a whole
+    step: E on a sample of FOV points, P and P^T on a sample of rays, the
+    VJP on a sample of the index set, the sampler on a sample of draws, Adam
+    on all parameters."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import adam as oadam
+    from oracle import geometry as ogeo
+    from oracle import grid as ogrid
+    from oracle import inr as oinr
+    from oracle import joseph
+    from oracle import sampler as osampler
+    from paper_2604_09884_amd import synth
+
+    rng = np.random.default_rng(0)
+    theta, B = synth.init_inr(p.arch, p.seed_init)
+    n = p.n_fov()
+    k = p.k(n)
+    m = p.n_rays
+    fov2 = ogrid.fov_indices(2, p.N)
+    budget = target_s / 5.0
+
+    def timed(fn):
+        t = time.perf_counter()
+        fn()
+        return time.perf_counter() - t
+
+    # E: oracle forward on S points (grow S until ~budget)
+    S = 2048
+    while True:
+        pts = fov2[rng.choice(fov2.size, size=S)] + rng.integers(0, p.N, S) * p.N * p.N
+        X = ogrid.coords(3, p.N, pts)
+        t_e = timed(lambda: oinr.forward(theta, B, X, p.arch))
+        if t_e > budget / 2 or S >= 1 << 18:
+            break
+        S *= 2
+    per_E = t_e / S * n
+    # P and P^T on R rays of view 0
+    R = 1024
+    p0, d = ogeo.cone3d_rays(p.n_views, p.n_u, p.n_v, p.du, p.dv, p.dso, p.dod,
+                             views=[0], rows=np.arange(p.n_v // 2 - 1, p.n_v // 2 + 1))
+    sel = rng.choice(p0.shape[0], size=R, replace=False)
+    t0 = time.perf_counter()
+    A = joseph.system_matrix(p.N, 3, p0[sel], d[sel])
+    t_build = time.perf_counter() - t0
+    vol = np.ones(p.N ** 3)
+    t_p = t_build + timed(lambda: A @ vol)
+    r = rng.standard_normal(R)
+    t_pt = t_build + timed(lambda: A.T @ r)
+    del vol
+    per_P = t_p / R * m
+    per_PT = t_pt / R * m
+    # VJP on Q sampled points
+    Q = 1024
+    Xq = ogrid.coords(3, p.N, fov2[rng.choice(fov2.size, size=Q)] + (p.N // 2) * p.N * p.N)
+    t_v = timed(lambda: oinr.vjp(theta, B, Xq, rng.standard_normal(Q), p.arch))
+    per_V = t_v / Q * k
+    # sampler on D draws
+    D = 2000
+    t_s = timed(lambda: osampler.sample_ranks(n, D, 1, 0))
+    per_S = t_s / D * k
+    # Adam on all parameters
+    t_a = timed(lambda: oadam.adam_update(theta, np.zeros_like(theta), np.zeros_like(theta),
+                                          theta, 1, 1e-3))
+    total = per_E + per_P + per_PT + per_V + per_S + t_a
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {
+        "value": 1.0 / total, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+        "sample": ("FP64 oracle on a bounded sample scaled to one full step: E on %d FOV "
+                   "points (x%.0f), P and P^T on %d rays (x%.0f), VJP on %d samples "
+                   "(x%.0f), sampler on %d draws, Adam on all %d parameters; "
+                   "est. %.1f s per step (E %.1f s, P %.1f s, P^T %.1f s, VJP %.1f s)"
+                   % (S, n / S, R, m / R, Q, k / Q, D, theta.size, total, per_E, per_P,
+                      per_PT, per_V)),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % a.gpus, flush=True)
+        sys.exit(2)
+    import torch
+
+    from paper_2604_09884_amd import configs, lib as L, ops, synth
+
+    p = configs.CONFIGS[a.config]
+    dtype = a.mlp_dtype or p.mlp_dtype
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    theta, B = synth.init_inr(p.arch, p.seed_init)
+    y = synth.sinogram(p).astype(np.float32)
+    log("inputs synthesised in %.1f s" % (time.time() - t0))
+    free0, total_mem = torch.cuda.mem_get_info()
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    Bd = torch.tensor(B.ravel() if B.size else np.zeros(1), dtype=torch.float32, device=dev)
+    yd = torch.tensor(y.ravel(), device=dev)
+    model = ops.Model(p.arch, p.dim, p.N, dtype, max_k=p.k())
+    geom = ops.Geometry(p)
+    k = p.k(model.n_fov)
+    v_mode = L.INRCT_V_FULL if a.v_mode == "full" else L.INRCT_V_AT_I
+    st = ops.GradStepper(model, geom, th, Bd, yd, k, p.lr, seed=p.seed_sampler, v_mode=v_mode)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    log("n_fov %d, k %d, params %d, device memory in use %.2f GB"
+        % (model.n_fov, k, model.n_params, (free0 - free1) / 1e9))
+
+    for t in range(a.warmup):
+        st.step(t)
+    torch.cuda.synchronize()
+    log("warmup done (%d steps), loss %.6g" % (a.warmup, float(st.loss)))
+    st.enable_timing(max(1, a.steps))
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for t in range(a.steps):
+        st.step(a.warmup + t)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    stages = st.stage_ms()
+    ms_step = wall * 1e3 / a.steps
+    loss = float(st.loss)
+    log("timed %d steps: %.2f ms/step, loss %.6g, stages %s"
+        % (a.steps, ms_step, loss, {k_: round(v / a.steps, 3) for k_, v in stages.items()}))
+
+    flop_per_point = p.arch.flops_forward()
+    e_ms = stages["eval_grid"] / a.steps
+    achieved = model.n_fov * flop_per_point / (e_ms * 1e-3)
+    roofline = {"bound": "mfma", "kernel": "k_eval_grid (grid evaluation E)",
+                "achieved": achieved / 1e12, "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[dtype], "traffic": None,
+                "per_unit": "%d FLOP per FOV point x %d points per launch"
+                            % (flop_per_point, model.n_fov),
+                "avg_launch_ms": e_ms}
+    out = {
+        "metric": "grad steps/s at 501^3 cone-beam 20 views",
+        "value": 1e3 / ms_step,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded ellipsoid phantom, closed-form chord data, Poisson 1e5)",
+        "config": {"workload": p.name, "grid": "%d^%d" % (p.N, p.dim),
+                   "views": p.n_views, "detector": "%dx%d" % (p.n_v, p.n_u),
+                   "n_fov": model.n_fov, "k": k, "params": model.n_params,
+                   "v_mode": a.v_mode, "parallelism": "single GPU"},
+        "stages_ms_per_step": {k_: v / a.steps for k_, v in stages.items()},
+        "device_mem_gb": (free0 - free1) / 1e9,
+        "loss_last": loss,
+        "roofline": roofline,
+    }
+    if not a.no_cpu and a.config in ("c1", "c2", "c3", "c4") and p.dim == 3:
+        log("timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

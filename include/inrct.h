@@ -1,0 +1,259 @@
+/*
+ * inrct.h -- C ABI of the memory-efficient INR gradient step for CT
+ * (Najaf & Ongie, "Memory-efficient optimization of implicit neural
+ * representations for CT reconstruction").
+ *
+ * The library evaluates the problem of Eq. (1), min_theta L(P{f_theta}, y),
+ * with the gradient of Algorithm 1 (Eq. (2) and Eq. (3)):
+ *   u = E{f_theta}      grid evaluation of the INR on the FOV  (inr_eval_grid)
+ *   z = P u             ray-driven Joseph projector             (ct_project)
+ *   r = dL/dz           LS residual z - y (FLS: ramp-filtered)  (inrct_residual_loss)
+ *   v = P^T r           matched voxel-driven adjoint            (ct_backproject)
+ *   I                   uniform k-subset of the FOV points      (inrct_sample)
+ *   g = (n/k) sum_{i in I} v_i grad f_theta(x_i)                (inr_vjp_subsampled)
+ *   theta <- Adam(theta, g)                                     (inrct_adam)
+ * and all of it in one call on a context (inr_grad_step).
+ *
+ * Conventions for every entry point
+ *  - Pointers named as device pointers must point to device memory of the
+ *    current HIP device; the caller owns them.  Host pointers are read
+ *    before the call returns and may be freed afterwards.
+ *  - Calls that take a hipStream_t only enqueue work on that stream; none
+ *    synchronises with the host and none allocates device memory.  Device
+ *    memory is allocated only by the *_create functions.
+ *  - Outputs are overwritten, never accumulated into.
+ *  - A handle (geometry, model, context) owns scratch memory; it may be used
+ *    by one stream at a time.  Calls that overlap on different streams must
+ *    use different handles.
+ *  - Every entry point returns INRCT_OK (0) or a negative status; after an
+ *    error, inrct_last_error() returns a message (thread-local).  Argument
+ *    errors are detected on the host before anything is enqueued.
+ *  - Results are deterministic: no kernel uses atomics; every reduction has
+ *    a fixed order.
+ *
+ * Data layouts (all float32 unless stated)
+ *  - grid arrays (u, v): [N][N] (2D) or [N][N][N] (3D), x fastest; the grid
+ *    spans [-1, 1]^d with pitch h = 2/N and centres -1 + (i + 1/2) h.
+ *  - FOV: the disc x^2 + y^2 <= 1 (2D) or that disc at every z (3D); the n
+ *    FOV points are ranked by ascending grid index.
+ *  - projection arrays (y, z, r): [V][Nu] (2D) or [V][Nv][Nu] (3D), u fastest.
+ *  - INR parameters theta: for each affine layer in order, W (fan_out x
+ *    fan_in, row-major) then b, output layer last.  FFN layer 1 reads the
+ *    encoding [sin(2 pi B x); cos(2 pi B x)] (sin block first); B is
+ *    float32 [F][d], not trained.
+ *  - index sets: int32 grid linear indices, distinct, inside the FOV,
+ *    ascending.
+ */
+#ifndef INRCT_H
+#define INRCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define INRCT_OK 0
+#define INRCT_EINVAL (-1)   /* bad argument, shape or handle               */
+#define INRCT_ENOTSUP (-2)  /* unsupported geometry / architecture / dtype */
+#define INRCT_EHIP (-3)     /* HIP runtime error (message has the detail)  */
+#define INRCT_ENOMEM (-4)   /* device allocation failed in a *_create      */
+
+/* geometry kinds */
+#define INRCT_PAR2D 1       /* 2D parallel beam                            */
+#define INRCT_CONE3D 2      /* 3D circular cone beam, flat detector        */
+
+/* INR kinds and MLP precision */
+#define INRCT_FFN 1         /* Fourier features + ReLU MLP                 */
+#define INRCT_SIREN 2       /* sine-activated MLP                          */
+#define INRCT_FP32 0        /* FP32 matrix cores                           */
+#define INRCT_BF16 1        /* BF16 matrix cores, FP32 accumulation        */
+
+/* losses (Sec. II) */
+#define INRCT_LS 0          /* 1/2 ||z - y||^2                             */
+#define INRCT_FLS 1         /* 1/2 (z - y)^T F (z - y), F = ramp filter    */
+
+/* how inr_grad_step forms v (both give the same g) */
+#define INRCT_V_FULL 0      /* v = P^T r on the whole grid, then gather v_I */
+#define INRCT_V_AT_I 1      /* evaluate (P^T r)_i only for i in I           */
+
+typedef struct {
+    int dim;                /* 2 or 3                                       */
+    int n;                  /* points per axis N (1..4096)                  */
+} inr_grid;
+
+/* Scan geometry.  View j sits at angle angles[j] (radians).
+ * PAR2D: ray direction (-sin, cos), detector axis (cos, sin); bin k at
+ *        (k - (n_u-1)/2) du; n_v must be 1.
+ * CONE3D: source sid (cos, sin, 0), detector centre -idd (cos, sin, 0),
+ *        detector axes (-sin, cos, 0) and (0, 0, 1); pixel (a, b) at
+ *        ((a - (n_u-1)/2) du, (b - (n_v-1)/2) dv). */
+typedef struct {
+    int kind;
+    int n_views, n_u, n_v;
+    double du, dv;
+    double sid, idd;        /* cone only                                    */
+    const double *angles;   /* HOST array [n_views]                         */
+} ct_geometry;
+
+typedef struct {
+    int kind;               /* INRCT_FFN or INRCT_SIREN                     */
+    int in_dim;             /* d = 2 or 3 (must equal the grid's dim)       */
+    int n_freq;             /* FFN: F (encoding width 2F, F % 8 == 0)       */
+    int width;              /* hidden width: 128 or 256                     */
+    int depth;              /* hidden layers L (1..8)                       */
+    float omega0;           /* SIREN frequency factor                       */
+    int mlp_dtype;          /* INRCT_FP32 or INRCT_BF16                     */
+} inr_arch;
+
+typedef struct inrct_geom inrct_geom;
+typedef struct inrct_model inrct_model;
+typedef struct inr_ctx inr_ctx;
+
+/* Message for the most recent error on this thread ("" if none). */
+const char *inrct_last_error(void);
+
+/* ------------------------------------------------------------------ P, P^T
+ * Joseph's ray-driven projector (Sec. III: P in R^{m x n}, a discrete
+ * approximation of ray integrals).  Per ray: one sample per grid slice
+ * along the principal axis (y if |d_y| >= (1 - 1e-9)|d_x|, else x; decided
+ * in float64 on the host), linear (2D) or bilinear (3D) interpolation with
+ * zero padding at fractional index (q + 1)/h - 1/2, times the step length
+ * h |d| / |d_axis|.  Interpolation positions are stepped in 32.32 fixed
+ * point from float64 ray parameters, so P and P^T see identical weights.
+ */
+
+/* Builds the geometry tables (host float64) and uploads them; allocates the
+ * handle's device scratch.  `g` and `grid` are copied. */
+int inrct_geom_create(const ct_geometry *g, const inr_grid *grid,
+                      inrct_geom **out);
+int inrct_geom_destroy(inrct_geom *geom);
+/* number of rays m = n_views * n_v * n_u */
+int64_t inrct_geom_n_rays(const inrct_geom *geom);
+
+/* z = P u.  u: device [grid], z: device [rays].  The whole grid is
+ * integrated (values outside the FOV count). */
+int ct_project(inrct_geom *geom, const float *u, float *z, hipStream_t stream);
+
+/* v = P^T r, the exact transpose of ct_project (Sec. III, v = P^T r),
+ * evaluated voxel by voxel as a gather over the rays whose interpolation
+ * stencil touches the voxel (no atomics).  r: device [rays]; v: device
+ * [grid], every grid point written. */
+int ct_backproject(inrct_geom *geom, const float *r, float *v,
+                   hipStream_t stream);
+
+/* v_I = (P^T r)_i for the k grid indices idx (device int32); v_out device
+ * [k].  Same arithmetic as ct_backproject at those voxels. */
+int ct_backproject_at(inrct_geom *geom, const float *r, const int32_t *idx,
+                      int64_t k, float *v_out, hipStream_t stream);
+
+/* r = dL/dz and L (Sec. II; Sec. III note after Algorithm 1).
+ * loss == INRCT_LS: r = z - y, L = 1/2 sum r^2.
+ * loss == INRCT_FLS: q = z - y, r = F q with F the Ram-Lak ramp along the
+ * detector-u index of every (view, row) (linear convolution, taps
+ * f0 = 1/(4 du), f_j = -1/(pi^2 j^2 du) for odd j), L = 1/2 q.r.
+ * z, y, r: device [rays] (r may alias z); loss_out: device double,
+ * accumulated in float64 with a fixed-order reduction. */
+int inrct_residual_loss(inrct_geom *geom, int loss, const float *z,
+                        const float *y, float *r, double *loss_out,
+                        hipStream_t stream);
+
+/* ------------------------------------------------------------------ E, VJP
+ * INR f_theta (Sec. IV: FFN and SIREN) evaluated with matrix-core GEMMs.
+ * `max_k` bounds the k of later inr_vjp_subsampled / inrct_sample calls
+ * (it sizes the handle's scratch).  `arch` and `grid` are copied. */
+int inrct_model_create(const inr_arch *arch, const inr_grid *grid,
+                       int64_t max_k, inrct_model **out);
+int inrct_model_destroy(inrct_model *model);
+int64_t inrct_model_n_params(const inrct_model *model);
+int64_t inrct_model_n_fov(const inrct_model *model);
+
+/* u = E{f_theta} (Sec. III): f_theta at every FOV point, 0 elsewhere, no
+ * autodiff state kept.  theta: device [p]; B: device [F][d] (FFN) or NULL;
+ * u: device [grid]. */
+int inr_eval_grid(inrct_model *model, const float *theta, const float *B,
+                  float *u, hipStream_t stream);
+
+/* f_theta at k grid points idx (device int32) -> f_out device [k]. */
+int inr_eval_points(inrct_model *model, const float *theta, const float *B,
+                    const int32_t *idx, int64_t k, float *f_out,
+                    hipStream_t stream);
+
+/* grad = scale * sum_{j<k} v_j grad_theta f_theta(x_{idx_j}) -- Eq. (2)
+ * with scale = n/|I|, equivalently the gradient of the virtual loss of
+ * Eq. (3).  Layer activations are recomputed per tile of points and never
+ * stored for the whole set.  v: device; if v_compact is 0 it is a full
+ * grid indexed by idx, else it holds the k values v_{idx_j} in order.
+ * grad: device [p], overwritten. */
+int inr_vjp_subsampled(inrct_model *model, const float *theta,
+                       const float *B, const int32_t *idx, int64_t k,
+                       const float *v, int v_compact, double scale,
+                       float *grad, hipStream_t stream);
+
+/* I (Algorithm 1, "sample random index set"): the first k images of the
+ * keyed pseudo-random permutation pi_{seed,step} of the FOV ranks [0, n),
+ * sorted, as grid indices.  pi: SplitMix64-keyed 6-round Feistel network
+ * on 2*hb bits (2^(2hb) >= n, hb = ceil(b/2), b = max(2, ceil(log2 n)))
+ * with cycle walking; round key K_r = mix64(seed ^ mix64(step ^
+ * (0x9E3779B97F4A7C15 (r+1)))), round function mix64(K_r ^ R) >> (64 -
+ * hb).  idx_out: device int32 [k]; 1 <= k <= min(n, max_k). */
+int inrct_sample(inrct_model *model, uint64_t seed, uint64_t step, int64_t k,
+                 int32_t *idx_out, hipStream_t stream);
+
+/* Adam (Kingma & Ba; the paper's optimiser, Sec. IV) with bias correction,
+ * t the 1-based step.  theta, m, v, g: device [p]; theta, m, v updated in
+ * place.  gnorm2_out: device double, ||g||^2 reduced in float64 (may be
+ * NULL). */
+int inrct_adam(inrct_model *model, float *theta, float *m, float *v,
+               const float *g, int64_t t, double lr, double beta1,
+               double beta2, double eps, double *gnorm2_out,
+               hipStream_t stream);
+
+/* ------------------------------------------------------------ full step */
+typedef struct {
+    int loss;               /* INRCT_LS or INRCT_FLS                        */
+    int64_t k;              /* |I|; k == n is full sampling                 */
+    uint64_t seed;          /* sampler key                                  */
+    double lr, beta1, beta2, eps;
+    int v_mode;             /* INRCT_V_FULL or INRCT_V_AT_I                 */
+} inrct_step_cfg;
+
+/* A context binds a model, a geometry and caller-owned device buffers
+ * theta [p], adam_m [p], adam_v [p], B [F][d] (or NULL) and y [rays].  It
+ * allocates its own u, z/r, v, g and I buffers. */
+int inr_ctx_create(inrct_model *model, inrct_geom *geom,
+                   const inrct_step_cfg *cfg, float *theta, float *adam_m,
+                   float *adam_v, const float *B, const float *y,
+                   inr_ctx **out);
+int inr_ctx_destroy(inr_ctx *ctx);
+
+/* One Algorithm-1 gradient estimate followed by one Adam update, all on
+ * `stream`: u = E f; z = P u; r, L; v = P^T r; I = sample(seed, step);
+ * g = (n/k) sum_I v_i grad f(x_i); theta <- Adam(theta, g) with t =
+ * step + 1.  loss_out, gnorm2_out: device doubles (L at the incoming theta
+ * and ||g||^2), either may be NULL. */
+int inr_grad_step(inr_ctx *ctx, uint64_t step, double *loss_out,
+                  double *gnorm2_out, hipStream_t stream);
+
+/* Stage timing with HIP events recorded on the step's stream, for
+ * measurement.  After inr_ctx_enable_timing(ctx, max_steps), each
+ * inr_grad_step records events around its stages (slots reused modulo
+ * max_steps).  inr_ctx_stage_ms waits for the recorded events, writes the
+ * summed milliseconds of stages 0..n_stages-1 over the recorded steps and
+ * starts a new recording.  Stages: 0 grid-evaluation kernel, 1 P, 2
+ * residual, 3 sampler, 4 P^T, 5 VJP, 6 Adam, 7 whole step. */
+int inr_ctx_enable_timing(inr_ctx *ctx, int max_steps);
+int inr_ctx_stage_ms(inr_ctx *ctx, int n_stages, double *ms_out);
+
+/* Device buffers owned by the context (valid until inr_ctx_destroy), for
+ * inspection: which = 0 u [grid], 1 r [rays], 2 v [grid or k], 3 g [p],
+ * 4 I [k] (int32). */
+void *inr_ctx_buffer(inr_ctx *ctx, int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* INRCT_H */

@@ -1,0 +1,962 @@
+// INR f_theta on matrix cores: grid evaluation E (Sec. III), point
+// evaluation, and the subsampled Jacobian-transpose product of Eq. (2).
+//
+// Layout of the forward GEMMs.  Every hidden layer is Y^T = W A^T with the
+// output features as the MFMA M dimension (32-row tiles), the layer inputs
+// as K and 32 points as N.  A 32x32 MFMA result leaves, in lane l, point
+// l % 32 and rows 8*(r/4) + 4*(l/32) + r%4 (r = 0..15) of the tile.  Those
+// are exactly the K values lane l must supply as the next layer's B
+// operand if the next layer's K order is permuted accordingly, so
+// activations stay in registers from layer to layer and only the packed
+// weights (A operands, permuted on the device by k_pack) are read from
+// memory.  The bias is one extra K step whose B operand is the constant 1.
+//
+// Two precisions: BF16 operands with FP32 accumulation
+// (v_mfma_f32_32x32x16_bf16, 16 K per step) and FP32
+// (v_mfma_f32_32x32x2f32, 2 K per step).
+//
+// The VJP recomputes the forward pass per 32-point tile, stores the tile's
+// activations and back-propagated deltas for one bounded chunk of points,
+// then forms dW = delta A^T for every layer with a split-K MFMA GEMM over the
+// chunk's points.  Split-K partials accumulate across chunks in a fixed
+// order and are summed in a fixed order at the end: no atomics.
+#include <math.h>
+
+#include "model.h"
+
+namespace inrct {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+static const int kMaxDepth = 8;
+
+struct MlpDev {
+    int kind;        // INRCT_FFN / INRCT_SIREN
+    int d, F, W, L;  // input dim, frequencies, width, hidden layers
+    float omega0;
+    const void *frag;    // forward A fragments (layers 1..L for FFN, 2..L SIREN)
+    const void *fragT;   // transposed fragments for deltas (layers 2..L)
+    const float *w_out;  // [W]
+    const float *b_out;  // [1]
+    const float *W1;     // SIREN layer 1 [W][d]
+    const float *b1;     // SIREN layer 1 [W]
+    const float *B;      // FFN Fourier matrix [F][d]
+    long long off[kMaxDepth + 2];   // fragment offset of layer l (1-based)
+    long long offT[kMaxDepth + 2];
+    FovDev fov;
+};
+
+template <bool BF>
+struct Prec;
+
+template <>
+struct Prec<true> {
+    typedef bf16x8 Op;
+    static constexpr int KPS = 16;
+    typedef __bf16 Store;
+    static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Prec<false> {
+    typedef float Op;
+    static constexpr int KPS = 2;
+    typedef float Store;
+    static __device__ __forceinline__ f32x16 mma(Op a, Op b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// K steps of layer l (including the bias step) and of the transposed pass.
+__host__ __device__ inline int layer_K(int kind, int F, int d, int W, int l) {
+    return l == 1 ? (kind == INRCT_FFN ? 2 * F : d) : W;
+}
+__host__ __device__ inline int ksteps(int K, int kps) { return K / kps + 1; }
+
+// Row of the 32-row tile held by lane-half h in accumulator slot r.
+__host__ __device__ inline int crow(int r, int h) { return 8 * (r / 4) + 4 * h + (r % 4); }
+
+// Input feature of layer l >= 2 supplied at k-step s, lane-half h, slot p.
+__host__ __device__ inline int chain_feature(bool bf, int s, int h, int p) {
+    if (bf) {
+        const int r = 8 * (s % 2) + p;
+        return 32 * (s / 2) + crow(r, h);
+    }
+    const int r = s % 16;
+    return 32 * (s / 16) + crow(r, h);
+}
+
+// Encoding feature (column of W_1) at k-step s, lane-half h, slot p (FFN).
+__host__ __device__ inline int enc_feature(bool bf, int F, int s, int h, int p) {
+    if (bf) {
+        const int f = 8 * s + 4 * h + p / 2;
+        return (p % 2) == 0 ? f : F + f;
+    }
+    return h == 0 ? s : F + s;
+}
+
+// ------------------------------------------------------------ weight pack
+// One thread per (fragment, lane, slot).  theta layout: per layer W then b.
+__global__ void k_pack(MlpDev m, const float *__restrict__ theta, int bf, void *frag,
+                       void *fragT, long long nfrag, long long nfragT,
+                       const long long *__restrict__ loff,
+                       const int *__restrict__ flayer, const int *__restrict__ fmt,
+                       const int *__restrict__ fs) {
+    const int slots = bf ? 8 : 1;
+    const long long total = (nfrag + nfragT) * 64 * slots;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total) return;
+    const int p = (int)(t % slots);
+    const int lane = (int)((t / slots) % 64);
+    const long long fi = t / (slots * 64);
+    const bool trans = fi >= nfrag;
+    const int l = flayer[fi], mt = fmt[fi], s = fs[fi];
+    const int i = lane % 32, h = lane / 32;
+    const int W = m.W;
+    const int K = layer_K(m.kind, m.F, m.d, W, l);
+    const float *Wl = theta + loff[l];
+    const float *bl = Wl + (long long)K * W;
+    float val = 0.f;
+    if (!trans) {
+        const int o = 32 * mt + i;
+        const int KS = ksteps(K, bf ? 16 : 2);
+        if (s == KS - 1) {
+            val = (h == 0 && p == 0) ? bl[o] : 0.f;
+        } else {
+            const int col = (l == 1) ? enc_feature(bf, m.F, s, h, p) : chain_feature(bf, s, h, p);
+            val = Wl[(long long)o * K + col];
+        }
+    } else {
+        const int o = chain_feature(bf, s, h, p);  // output feature of layer l
+        val = Wl[(long long)o * K + 32 * mt + i];
+    }
+    const long long idx = (trans ? (fi - nfrag) : fi) * 64 + lane;
+    if (bf) {
+        __bf16 *dst = (__bf16 *)(trans ? fragT : frag);
+        dst[idx * 8 + p] = (__bf16)val;
+    } else {
+        float *dst = (float *)(trans ? fragT : frag);
+        dst[idx] = val;
+    }
+}
+
+// ---------------------------------------------------------- forward core
+template <int ACT>
+__device__ __forceinline__ float act_fn(float z, float w0) {
+    if constexpr (ACT == INRCT_FFN) return fmaxf(z, 0.f);
+    else return sinf(w0 * z);
+}
+template <int ACT>
+__device__ __forceinline__ float act_grad(float z, float w0) {
+    if constexpr (ACT == INRCT_FFN) return z > 0.f ? 1.f : 0.f;
+    else return w0 * cosf(w0 * z);
+}
+
+// sin and cos of 2 pi t (t in turns), reduced to [-1/2, 1/2] first.
+__device__ __forceinline__ void sincos_turns(float t, float *s, float *c) {
+    const float r = t - rintf(t);
+    *s = sinpif(2.f * r);
+    *c = cospif(2.f * r);
+}
+
+// Sink for activations / pre-activation derivatives during the VJP.
+template <bool BF>
+struct ActSink {
+    typename Prec<BF>::Store *act;  // base of activation scratch
+    float *sig;                     // SIREN derivative scratch (or null)
+    long long P;                    // points per chunk (row stride)
+    long long act_off[kMaxDepth + 2];
+    long long sig_off[kMaxDepth + 2];
+};
+
+template <int W, int NT, bool BF, int ACT, bool STORE>
+__device__ __forceinline__ void mlp_forward(const MlpDev &m, const float (&xc)[NT][3],
+                                            f32x16 (&acc)[NT][W / 32],
+                                            const ActSink<BF> &sink,
+                                            const int (&pcol)[NT]) {
+    typedef Prec<BF> PR;
+    typedef typename PR::Op Op;
+    constexpr int MT = W / 32;
+    constexpr int KPS = PR::KPS;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
+    const int L = m.L;
+    const Op *frag = (const Op *)m.frag;
+
+    Op one_b;
+    if constexpr (BF) {
+        for (int p = 0; p < 8; ++p) one_b[p] = (__bf16)((h == 0 && p == 0) ? 1.f : 0.f);
+    } else {
+        one_b = h == 0 ? 1.f : 0.f;
+    }
+
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
+
+    // ---------------- layer 1
+    if constexpr (ACT == INRCT_FFN) {
+        const int F = m.F;
+        const int KS = ksteps(2 * F, KPS);
+        const Op *fr = frag + m.off[1] * 64;
+        for (int s = 0; s < KS - 1; ++s) {
+            Op bop[NT];
+            if constexpr (BF) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int f = 8 * s + 4 * h + q;
+                    const float bx = m.B[f * m.d], by = m.B[f * m.d + 1];
+                    const float bz = m.d == 3 ? m.B[f * m.d + 2] : 0.f;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const float t = fmaf(bz, xc[nt][2], fmaf(by, xc[nt][1], bx * xc[nt][0]));
+                        float sn, cs;
+                        sincos_turns(t, &sn, &cs);
+                        bop[nt][2 * q] = (__bf16)sn;
+                        bop[nt][2 * q + 1] = (__bf16)cs;
+                        if constexpr (STORE) {
+                            if (pcol[nt] >= 0) {
+                                sink.act[sink.act_off[0] + (long long)f * sink.P + pcol[nt]] = (__bf16)sn;
+                                sink.act[sink.act_off[0] + (long long)(F + f) * sink.P + pcol[nt]] = (__bf16)cs;
+                            }
+                        }
+                    }
+                }
+            } else {
+                const int f = s;
+                const float bx = m.B[f * m.d], by = m.B[f * m.d + 1];
+                const float bz = m.d == 3 ? m.B[f * m.d + 2] : 0.f;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float t = fmaf(bz, xc[nt][2], fmaf(by, xc[nt][1], bx * xc[nt][0]));
+                    float sn, cs;
+                    sincos_turns(t, &sn, &cs);
+                    bop[nt] = h == 0 ? sn : cs;
+                    if constexpr (STORE) {
+                        if (pcol[nt] >= 0)
+                            sink.act[sink.act_off[0] + (long long)(h == 0 ? f : F + f) * sink.P + pcol[nt]] = bop[nt];
+                    }
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const Op a = fr[((long long)mt * KS + s) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, bop[nt], acc[nt][mt]);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const Op a = fr[((long long)mt * KS + KS - 1) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, one_b, acc[nt][mt]);
+        }
+    } else {
+        // SIREN layer 1 on the vector units: z = W1 x + b1 in C layout
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int o = 32 * mt + crow(r, h);
+                const float w0 = m.W1[o * m.d], w1 = m.W1[o * m.d + 1];
+                const float w2 = m.d == 3 ? m.W1[o * m.d + 2] : 0.f;
+                const float bb = m.b1[o];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[nt][mt][r] = fmaf(w2, xc[nt][2], fmaf(w1, xc[nt][1], fmaf(w0, xc[nt][0], bb)));
+            }
+        if constexpr (STORE) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                if (h == 0 && pcol[nt] >= 0)
+                    for (int c = 0; c < m.d; ++c)
+                        sink.act[sink.act_off[0] + (long long)c * sink.P + pcol[nt]] =
+                            (typename PR::Store)xc[nt][c];
+        }
+    }
+
+    // ---------------- layers 2..L
+    for (int l = 2; l <= L; ++l) {
+        constexpr int NS = W / KPS;  // k-steps without bias
+        Op bin[NT][NS];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if constexpr (BF) {
+#pragma unroll
+                    for (int p = 0; p < 8; ++p) {
+                        const float z = acc[nt][s / 2][8 * (s % 2) + p];
+                        bin[nt][s][p] = (__bf16)act_fn<ACT>(z, m.omega0);
+                    }
+                } else {
+                    const float z = acc[nt][s / 16][s % 16];
+                    bin[nt][s] = act_fn<ACT>(z, m.omega0);
+                }
+            }
+            if constexpr (STORE) {
+                // a_{l-1} and (SIREN) its derivative factor, natural row order
+                if (pcol[nt] >= 0) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = 32 * mt + crow(r, h);
+                            const float z = acc[nt][mt][r];
+                            sink.act[sink.act_off[l - 1] + (long long)row * sink.P + pcol[nt]] =
+                                (typename PR::Store)act_fn<ACT>(z, m.omega0);
+                            if constexpr (ACT == INRCT_SIREN)
+                                sink.sig[sink.sig_off[l - 1] + (long long)row * sink.P + pcol[nt]] =
+                                    act_grad<ACT>(z, m.omega0);
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
+        const int KS = NS + 1;
+        const Op *fr = frag + m.off[l] * 64;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const Op a = fr[((long long)mt * KS + s) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, bin[nt][s], acc[nt][mt]);
+            }
+            const Op a = fr[((long long)mt * KS + NS) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, one_b, acc[nt][mt]);
+        }
+    }
+}
+
+// f = w_out . act(z_L) + b_out for the lane's point (both halves combined).
+template <int W, int NT, int ACT>
+__device__ __forceinline__ void mlp_output(const MlpDev &m, const f32x16 (&acc)[NT][W / 32],
+                                           float (&f)[NT]) {
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        float s = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < W / 32; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                s = fmaf(m.w_out[32 * mt + crow(r, h)], act_fn<ACT>(acc[nt][mt][r], m.omega0), s);
+        s += __shfl_xor(s, 32);
+        f[nt] = s + m.b_out[0];
+    }
+}
+
+__device__ __forceinline__ float grid_coord(int i, int N) {
+    return (float)(2 * i + 1 - N) / (float)N;
+}
+
+// ------------------------------------------------------- E on the grid
+// Each wave evaluates 32*NT consecutive FOV ranks.
+template <int W, int NT, bool BF, int ACT>
+__global__ __launch_bounds__(256) void k_eval_grid(MlpDev m, long long n, float *__restrict__ u) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const long long base = ((long long)blockIdx.x * 4 + wave) * (32 * NT);
+    if (base >= n) return;
+    float xc[NT][3];
+    long long gidx[NT];
+    int pcol[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        long long q = base + nt * 32 + (lane & 31);
+        const bool ok = q < n;
+        if (!ok) q = n - 1;
+        int ix, iy, iz;
+        gidx[nt] = fov_rank_to_index(m.fov, q, &ix, &iy, &iz);
+        if (!ok) gidx[nt] = -1;
+        xc[nt][0] = grid_coord(ix, m.fov.N);
+        xc[nt][1] = grid_coord(iy, m.fov.N);
+        xc[nt][2] = m.fov.dim == 3 ? grid_coord(iz, m.fov.N) : 0.f;
+        pcol[nt] = -1;
+    }
+    f32x16 acc[NT][W / 32];
+    ActSink<BF> sink{};
+    mlp_forward<W, NT, BF, ACT, false>(m, xc, acc, sink, pcol);
+    float f[NT];
+    mlp_output<W, NT, ACT>(m, acc, f);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+        if (lane < 32 && gidx[nt] >= 0) u[gidx[nt]] = f[nt];
+}
+
+// zero every grid point outside the FOV
+__global__ void k_zero_outside(FovDev f, float *__restrict__ u, long long ngrid) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ngrid) return;
+    const int x = (int)(t % f.N);
+    const int y = (int)((t / f.N) % f.N);
+    const int cnt = f.row_start[y + 1] - f.row_start[y];
+    const int lo = f.xlo[y];
+    if (x < lo || x >= lo + cnt) u[t] = 0.f;
+}
+
+__device__ __forceinline__ void index_coords(const FovDev &f, long long g, float *xc) {
+    const int N = f.N;
+    const int ix = (int)(g % N), iy = (int)((g / N) % N), iz = (int)(g / ((long long)N * N));
+    xc[0] = grid_coord(ix, N);
+    xc[1] = grid_coord(iy, N);
+    xc[2] = f.dim == 3 ? grid_coord(iz, N) : 0.f;
+}
+
+// f at listed grid indices
+template <int W, int NT, bool BF, int ACT>
+__global__ __launch_bounds__(256) void k_eval_points(MlpDev m, const int32_t *__restrict__ idx,
+                                                     long long k, float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const long long base = ((long long)blockIdx.x * 4 + wave) * (32 * NT);
+    if (base >= k) return;
+    float xc[NT][3];
+    long long j[NT];
+    int pcol[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        j[nt] = base + nt * 32 + (lane & 31);
+        const long long jj = j[nt] < k ? j[nt] : k - 1;
+        index_coords(m.fov, idx[jj], xc[nt]);
+        pcol[nt] = -1;
+    }
+    f32x16 acc[NT][W / 32];
+    ActSink<BF> sink{};
+    mlp_forward<W, NT, BF, ACT, false>(m, xc, acc, sink, pcol);
+    float f[NT];
+    mlp_output<W, NT, ACT>(m, acc, f);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+        if (lane < 32 && j[nt] < k) out[j[nt]] = f[nt];
+}
+
+// ------------------------------------------------ VJP phase 1: fwd + deltas
+// Points j0 .. j0 + P of the index list form the chunk; column c of the
+// scratch holds point j0 + c (columns past k carry a zero cotangent).
+template <int W, int NT, bool BF, int ACT>
+__global__ __launch_bounds__(256) void k_vjp_tile(MlpDev m, const int32_t *__restrict__ idx,
+                                                  long long k, long long j0,
+                                                  const float *__restrict__ v, int v_compact,
+                                                  float scale, long long ncols,
+                                                  ActSink<BF> sink,
+                                                  typename Prec<BF>::Store *__restrict__ dlt,
+                                                  long long dlt_off_L1) {
+    typedef Prec<BF> PR;
+    typedef typename PR::Op Op;
+    typedef typename PR::Store St;
+    constexpr int MT = W / 32;
+    constexpr int KPS = PR::KPS;
+    constexpr int NS = W / KPS;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
+    const int wave = threadIdx.x >> 6;
+    const long long cbase = ((long long)blockIdx.x * 4 + wave) * (32 * NT);
+    if (cbase >= ncols) return;
+    float xc[NT][3];
+    float cot[NT];
+    int pcol[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        pcol[nt] = (int)(cbase + nt * 32 + (lane & 31));
+        const long long jg = j0 + pcol[nt];
+        const bool ok = jg < k;
+        const long long jj = ok ? jg : k - 1;
+        const long long g = idx[jj];
+        index_coords(m.fov, g, xc[nt]);
+        cot[nt] = ok ? scale * (v_compact ? v[jj] : v[g]) : 0.f;
+    }
+    f32x16 acc[NT][MT];
+    mlp_forward<W, NT, BF, ACT, true>(m, xc, acc, sink, pcol);
+    const int L = m.L;
+    const long long P = sink.P;
+    // dlt rows: layer l (1..L) at dlt + (l-1)*W*P, output layer at dlt_off_L1
+    // ---- output layer: delta_{L+1} = cot; store a_L (+ SIREN factor)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        if (h == 0) dlt[dlt_off_L1 + pcol[nt]] = (St)cot[nt];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * mt + crow(r, h);
+                const float z = acc[nt][mt][r];
+                sink.act[sink.act_off[L] + (long long)row * P + pcol[nt]] = (St)act_fn<ACT>(z, m.omega0);
+                // delta_L = cot * w_out * act'(z_L)
+                const float dl = cot[nt] * m.w_out[row] * act_grad<ACT>(z, m.omega0);
+                acc[nt][mt][r] = dl;
+                dlt[(long long)(L - 1) * W * P + (long long)row * P + pcol[nt]] = (St)dl;
+            }
+    }
+    const Op *fragT = (const Op *)m.fragT;
+    for (int l = L; l >= 2; --l) {
+        Op bin[NT][NS];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if constexpr (BF) {
+#pragma unroll
+                    for (int p = 0; p < 8; ++p) bin[nt][s][p] = (__bf16)acc[nt][s / 2][8 * (s % 2) + p];
+                } else {
+                    bin[nt][s] = acc[nt][s / 16][s % 16];
+                }
+            }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
+        const Op *fr = fragT + m.offT[l] * 64;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const Op a = fr[((long long)mt * NS + s) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, bin[nt][s], acc[nt][mt]);
+            }
+        // delta_{l-1} = (W_l^T delta_l) * act'(z_{l-1})
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 32 * mt + crow(r, h);
+                    const long long e = (long long)row * P + pcol[nt];
+                    float g;
+                    if constexpr (ACT == INRCT_FFN) g = (float)sink.act[sink.act_off[l - 1] + e] > 0.f ? 1.f : 0.f;
+                    else g = sink.sig[sink.sig_off[l - 1] + e];
+                    const float dl = acc[nt][mt][r] * g;
+                    acc[nt][mt][r] = dl;
+                    dlt[(long long)(l - 2) * W * P + e] = (St)dl;
+                }
+    }
+}
+
+// ------------------------------------------------ VJP phase 2: dW GEMMs
+// Tile table entry: layer, M rows (delta rows), R inputs (act rows; column R
+// is the bias), tile origin.
+struct GemmTile {
+    long long dlt_off;   // element offset of delta_l rows
+    long long act_off;   // element offset of a_{l-1} rows
+    int M, R, tm, tn;    // rows, inputs, tile origin (rows, cols)
+    long long theta_off; // parameter offset of layer l (W then b)
+};
+
+template <bool BF>
+__global__ __launch_bounds__(256) void k_dw_gemm(const GemmTile *__restrict__ tiles,
+                                                 const typename Prec<BF>::Store *__restrict__ dlt,
+                                                 const typename Prec<BF>::Store *__restrict__ act,
+                                                 long long P, long long ncols, int kslice,
+                                                 int accumulate,
+                                                 float *__restrict__ part, int ntiles) {
+    typedef Prec<BF> PR;
+    typedef typename PR::Op Op;
+    typedef typename PR::Store St;
+    constexpr int KPS = PR::KPS;
+    const GemmTile T = tiles[blockIdx.x];
+    const int ks = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, i = lane & 31;
+    const int wm = wave >> 1, wn = wave & 1;
+    const long long p0 = (long long)ks * kslice;
+    long long p1 = p0 + kslice;
+    if (p1 > ncols) p1 = ncols;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x16){0};
+    int rows[2], cols[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        rows[a] = T.tm + wm * 64 + a * 32 + i;
+        cols[a] = T.tn + wn * 64 + a * 32 + i;
+    }
+    for (long long p = p0; p < p1; p += KPS) {
+        Op A[2], B[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if constexpr (BF) {
+                if (rows[a] < T.M)
+                    A[a] = *(const Op *)(dlt + T.dlt_off + (long long)rows[a] * P + p + 8 * h);
+                else
+                    for (int q = 0; q < 8; ++q) A[a][q] = (__bf16)0.f;
+                if (cols[a] < T.R)
+                    B[a] = *(const Op *)(act + T.act_off + (long long)cols[a] * P + p + 8 * h);
+                else
+                    for (int q = 0; q < 8; ++q) B[a][q] = (__bf16)(cols[a] == T.R ? 1.f : 0.f);
+            } else {
+                A[a] = rows[a] < T.M ? dlt[T.dlt_off + (long long)rows[a] * P + p + h] : 0.f;
+                B[a] = cols[a] < T.R ? act[T.act_off + (long long)cols[a] * P + p + h]
+                                     : (cols[a] == T.R ? 1.f : 0.f);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = PR::mma(A[a], B[b], acc[a][b]);
+    }
+    float *out = part + ((long long)ks * ntiles + blockIdx.x) * (128 * 128);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int lr = wm * 64 + a * 32 + crow(r, h);
+                const int lc = wn * 64 + b * 32 + i;
+                float *o = out + lr * 128 + lc;
+                *o = accumulate ? *o + acc[a][b][r] : acc[a][b][r];
+            }
+}
+
+// grad[theta] = sum over k-slices (fixed order) of the tile partials
+__global__ void k_dw_reduce(const GemmTile *__restrict__ tiles, const float *__restrict__ part,
+                            int ntiles, int nks, float *__restrict__ grad) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)ntiles * 16384) return;
+    const int tile = (int)(t / 16384);
+    const int e = (int)(t % 16384);
+    const GemmTile T = tiles[tile];
+    const int row = T.tm + e / 128, col = T.tn + e % 128;
+    if (row >= T.M || col > T.R) return;
+    float s = 0.f;
+    for (int k = 0; k < nks; ++k) s += part[((long long)k * ntiles + tile) * 16384 + e];
+    const long long dst = col < T.R ? T.theta_off + (long long)row * T.R + col
+                                    : T.theta_off + (long long)T.M * T.R + row;
+    grad[dst] = s;
+}
+
+}  // namespace inrct
+
+// ==================================================================== host
+using namespace inrct;
+
+namespace inrct {
+
+static MlpDev make_dev(const inrct_model *m, const float *theta, const float *B) {
+    MlpDev d{};
+    d.kind = m->arch.kind;
+    d.d = m->arch.in_dim;
+    d.F = m->arch.n_freq;
+    d.W = m->arch.width;
+    d.L = m->arch.depth;
+    d.omega0 = m->arch.omega0;
+    d.frag = m->frag.ptr;
+    d.fragT = m->fragT.ptr;
+    const int L = m->arch.depth;
+    d.w_out = theta + m->loff[L + 1];
+    d.b_out = theta + m->loff[L + 1] + m->arch.width;
+    d.W1 = theta + m->loff[1];
+    d.b1 = theta + m->loff[1] + (long long)m->arch.in_dim * m->arch.width;
+    d.B = B;
+    for (int l = 0; l < 10 && l < kMaxDepth + 2; ++l) {
+        d.off[l] = m->frag_off[l];
+        d.offT[l] = m->fragT_off[l];
+    }
+    d.fov = m->fov.dev(m->dim);
+    return d;
+}
+
+void model_pack(inrct_model *m, const float *theta, hipStream_t s) {
+    const MlpDev d = make_dev(m, theta, nullptr);
+    const int slots = m->bf16() ? 8 : 1;
+    const long long total = (m->nfrag + m->nfragT) * 64 * slots;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, d, theta,
+                       m->bf16() ? 1 : 0, m->frag.ptr, m->fragT.ptr, m->nfrag, m->nfragT,
+                       m->d_loff.as<long long>(), m->pk_layer.as<int>(), m->pk_mt.as<int>(),
+                       m->pk_s.as<int>());
+    INRCT_CHECK_LAUNCH();
+}
+
+template <int W, int NT, bool BF, int ACT>
+static void launch_eval_grid(const MlpDev &d, long long n, float *u, hipStream_t s) {
+    const long long per_block = 4LL * 32 * NT;
+    hipLaunchKernelGGL((k_eval_grid<W, NT, BF, ACT>), dim3((unsigned)cdiv(n, per_block)), dim3(256),
+                       0, s, d, n, u);
+    INRCT_CHECK_LAUNCH();
+}
+
+template <int W, int NT, bool BF, int ACT>
+static void launch_eval_points(const MlpDev &d, const int32_t *idx, long long k, float *out,
+                               hipStream_t s) {
+    const long long per_block = 4LL * 32 * NT;
+    hipLaunchKernelGGL((k_eval_points<W, NT, BF, ACT>), dim3((unsigned)cdiv(k, per_block)),
+                       dim3(256), 0, s, d, idx, k, out);
+    INRCT_CHECK_LAUNCH();
+}
+
+#define INRCT_DISPATCH_ACT(m, FN, W_, BF_, ...)                                \
+    do {                                                                       \
+        if ((m)->arch.kind == INRCT_FFN) FN<W_, 1, BF_, INRCT_FFN>(__VA_ARGS__);  \
+        else FN<W_, 1, BF_, INRCT_SIREN>(__VA_ARGS__);                         \
+    } while (0)
+
+#define INRCT_DISPATCH_W_BF(m, FN, ...)                                        \
+    do {                                                                       \
+        if ((m)->arch.width == 256) {                                          \
+            if ((m)->bf16()) INRCT_DISPATCH_ACT(m, FN, 256, true, __VA_ARGS__); \
+            else INRCT_DISPATCH_ACT(m, FN, 256, false, __VA_ARGS__);           \
+        } else {                                                               \
+            if ((m)->bf16()) INRCT_DISPATCH_ACT(m, FN, 128, true, __VA_ARGS__); \
+            else INRCT_DISPATCH_ACT(m, FN, 128, false, __VA_ARGS__);           \
+        }                                                                      \
+    } while (0)
+
+void model_zero_outside(inrct_model *m, float *u, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_outside, dim3((unsigned)cdiv(m->n_grid, 256)), dim3(256), 0, s,
+                       m->fov.dev(m->dim), u, m->n_grid);
+    INRCT_CHECK_LAUNCH();
+}
+
+void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u,
+                    hipStream_t s) {
+    const MlpDev d = make_dev(m, theta, B);
+    INRCT_DISPATCH_W_BF(m, launch_eval_grid, d, m->n_fov, u, s);
+}
+
+void model_eval_grid(inrct_model *m, const float *theta, const float *B, float *u,
+                     hipStream_t s, bool pack) {
+    if (pack) model_pack(m, theta, s);
+    model_zero_outside(m, u, s);
+    model_eval_fov(m, theta, B, u, s);
+}
+
+static void model_eval_points(inrct_model *m, const float *theta, const float *B,
+                              const int32_t *idx, long long k, float *out, hipStream_t s) {
+    model_pack(m, theta, s);
+    const MlpDev d = make_dev(m, theta, B);
+    INRCT_DISPATCH_W_BF(m, launch_eval_points, d, idx, k, out, s);
+}
+
+template <int W, int NT, bool BF, int ACT>
+static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx, long long k,
+                             long long j0, long long ncols, const float *v, int v_compact,
+                             float scale, int accumulate, hipStream_t s) {
+    typedef typename Prec<BF>::Store St;
+    ActSink<BF> sink{};
+    sink.act = m->act.as<St>();
+    sink.sig = m->sig.as<float>();
+    sink.P = m->P_alloc;
+    for (int l = 0; l < 10 && l < kMaxDepth + 2; ++l) {
+        sink.act_off[l] = m->act_off[l];
+        sink.sig_off[l] = m->sig_off[l];
+    }
+    const long long P = m->P_alloc;
+    const long long dlt_L1 = (long long)m->arch.depth * m->arch.width * P;
+    const long long per_block = 4LL * 32 * NT;
+    hipLaunchKernelGGL((k_vjp_tile<W, NT, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
+                       dim3(256), 0, s, d, idx, k, j0, v, v_compact, scale, ncols, sink,
+                       m->dlt.as<St>(), dlt_L1);
+    INRCT_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_dw_gemm<BF>), dim3(m->ntiles, m->nks), dim3(256), 0, s,
+                       m->tiles.as<GemmTile>(), (const St *)m->dlt.ptr, (const St *)m->act.ptr,
+                       P, ncols, m->kslice, accumulate, m->part.as<float>(), m->ntiles);
+    INRCT_CHECK_LAUNCH();
+}
+
+void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t *idx,
+               long long k, const float *v, int v_compact, double scale, float *grad,
+               hipStream_t s, bool pack) {
+    if (pack) model_pack(m, theta, s);
+    const MlpDev d = make_dev(m, theta, B);
+    const long long P = m->P_alloc;
+    int chunk = 0;
+    for (long long j0 = 0; j0 < k; j0 += P, ++chunk) {
+        long long ncols = k - j0 < P ? k - j0 : P;
+        ncols = cdiv(ncols, 128) * 128;
+        if (ncols > P) ncols = P;
+        INRCT_DISPATCH_W_BF(m, launch_vjp_chunk, m, d, idx, k, j0, ncols, v, v_compact,
+                            (float)scale, chunk > 0 ? 1 : 0, s);
+    }
+    hipLaunchKernelGGL(k_dw_reduce, dim3((unsigned)cdiv((long long)m->ntiles * 16384, 256)),
+                       dim3(256), 0, s, m->tiles.as<GemmTile>(), m->part.as<float>(),
+                       m->ntiles, m->nks, grad);
+    INRCT_CHECK_LAUNCH();
+}
+
+}  // namespace inrct
+
+extern "C" {
+
+int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k,
+                       inrct_model **out) {
+    return guarded([&] {
+        INRCT_REQUIRE(arch && grid && out, "null argument");
+        *out = nullptr;
+        const inr_arch &a = *arch;
+        INRCT_REQUIRE(grid->dim == 2 || grid->dim == 3, "grid dim must be 2 or 3");
+        INRCT_REQUIRE(grid->n >= 1 && grid->n <= 4096, "grid n must be in [1, 4096]");
+        INRCT_REQUIRE(a.in_dim == grid->dim, "arch in_dim must equal the grid dim");
+        INRCT_REQUIRE(a.kind == INRCT_FFN || a.kind == INRCT_SIREN, "unknown INR kind %d", a.kind);
+        INRCT_REQUIRE(a.width == 128 || a.width == 256, "width must be 128 or 256");
+        INRCT_REQUIRE(a.depth >= 1 && a.depth <= kMaxDepth, "depth must be in [1, %d]", kMaxDepth);
+        INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32 || a.mlp_dtype == INRCT_BF16, "unknown mlp dtype");
+        if (a.kind == INRCT_FFN)
+            INRCT_REQUIRE(a.n_freq >= 8 && a.n_freq % 8 == 0 && a.n_freq <= 4096,
+                          "FFN needs n_freq a positive multiple of 8");
+        INRCT_REQUIRE(max_k >= 1, "max_k must be >= 1");
+        inrct_model *m = new inrct_model();
+        try {
+            m->arch = a;
+            m->N = grid->n;
+            m->dim = grid->dim;
+            m->n_grid = 1;
+            for (int i = 0; i < m->dim; ++i) m->n_grid *= m->N;
+            INRCT_REQUIRE(m->n_grid < (1LL << 31), "grid too large for int32 indices");
+            m->fov.build(m->dim, m->N);
+            m->n_fov = m->fov.n;
+            INRCT_REQUIRE(m->n_fov >= 1, "empty FOV");
+            m->max_k = std::min<long long>(max_k, m->n_fov);
+            const int W = a.width, L = a.depth, d = a.in_dim;
+            const bool bf = a.mlp_dtype == INRCT_BF16;
+            const int kps = bf ? 16 : 2;
+            // parameter offsets
+            m->loff.assign(L + 2, 0);
+            long long off = 0;
+            for (int l = 1; l <= L + 1; ++l) {
+                m->loff[l] = off;
+                const int K = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
+                const int O = l == L + 1 ? 1 : W;
+                off += (long long)K * O + O;
+            }
+            m->n_params = off;
+            upload(m->d_loff, m->loff);
+            // fragment tables
+            std::vector<int> fl, fm, fs;
+            const int MT = W / 32;
+            const int l_first = a.kind == INRCT_FFN ? 1 : 2;
+            for (int l = l_first; l <= L; ++l) {
+                const int KS = ksteps(layer_K(a.kind, a.n_freq, d, W, l), kps);
+                m->frag_off[l] = (long long)fl.size();
+                for (int mt = 0; mt < MT; ++mt)
+                    for (int s = 0; s < KS; ++s) {
+                        fl.push_back(l);
+                        fm.push_back(mt);
+                        fs.push_back(s);
+                    }
+            }
+            m->nfrag = (long long)fl.size();
+            for (int l = 2; l <= L; ++l) {
+                const int NS = W / kps;
+                m->fragT_off[l] = (long long)fl.size() - m->nfrag;
+                for (int mt = 0; mt < MT; ++mt)
+                    for (int s = 0; s < NS; ++s) {
+                        fl.push_back(l);
+                        fm.push_back(mt);
+                        fs.push_back(s);
+                    }
+            }
+            m->nfragT = (long long)fl.size() - m->nfrag;
+            upload(m->pk_layer, fl);
+            upload(m->pk_mt, fm);
+            upload(m->pk_s, fs);
+            const size_t fbytes = bf ? 16 : 4;
+            m->frag.alloc(std::max<long long>(1, m->nfrag) * 64 * fbytes);
+            m->fragT.alloc(std::max<long long>(1, m->nfragT) * 64 * fbytes);
+            // VJP scratch: chunk of P_alloc points
+            const long long kpad = cdiv(m->max_k, 128) * 128;
+            m->P_alloc = std::min<long long>(kpad, 65536);
+            m->nks = (int)cdiv(m->P_alloc, m->kslice);
+            const long long P = m->P_alloc;
+            const int K1 = layer_K(a.kind, a.n_freq, d, W, 1);
+            m->act_off[0] = 0;
+            for (int l = 1; l <= L; ++l) m->act_off[l] = (long long)K1 * P + (long long)(l - 1) * W * P;
+            m->act_elems = (long long)K1 * P + (long long)L * W * P;
+            m->dlt_elems = (long long)L * W * P + P;
+            const size_t es = bf ? 2 : 4;
+            m->act.alloc(m->act_elems * es);
+            m->dlt.alloc(m->dlt_elems * es);
+            if (a.kind == INRCT_SIREN) {
+                for (int l = 1; l <= L; ++l) m->sig_off[l] = (long long)(l - 1) * W * P;
+                m->sig_elems = (long long)L * W * P;
+                m->sig.alloc(m->sig_elems * sizeof(float));
+            }
+            // dW GEMM tiles: layer l = 1..L+1, delta rows M, inputs R (+ bias col)
+            std::vector<GemmTile> tiles;
+            for (int l = 1; l <= L + 1; ++l) {
+                GemmTile t{};
+                t.M = l == L + 1 ? 1 : W;
+                t.R = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
+                t.dlt_off = (long long)(l - 1) * W * P;
+                t.act_off = m->act_off[l - 1];
+                t.theta_off = m->loff[l];
+                for (int tm = 0; tm < t.M; tm += 128)
+                    for (int tn = 0; tn <= t.R; tn += 128) {
+                        GemmTile u = t;
+                        u.tm = tm;
+                        u.tn = tn;
+                        tiles.push_back(u);
+                    }
+            }
+            m->ntiles = (int)tiles.size();
+            upload(m->tiles, tiles);
+            m->part.alloc((size_t)m->nks * m->ntiles * 16384 * sizeof(float));
+            // sampler scratch
+            m->flags.alloc((size_t)m->n_fov);
+            m->n_blk = cdiv(m->n_fov, 4096);
+            m->blk.alloc((size_t)(m->n_blk + 1) * sizeof(int64_t));
+            // Adam partials
+            m->n_apart = (int)std::min<long long>(1024, std::max<long long>(1, cdiv(m->n_params, 2048)));
+            m->apart.alloc(sizeof(double) * m->n_apart);
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
+int inrct_model_destroy(inrct_model *model) {
+    delete model;
+    return INRCT_OK;
+}
+
+int64_t inrct_model_n_params(const inrct_model *model) { return model ? model->n_params : -1; }
+int64_t inrct_model_n_fov(const inrct_model *model) { return model ? model->n_fov : -1; }
+
+int inr_eval_grid(inrct_model *model, const float *theta, const float *B, float *u,
+                  hipStream_t stream) {
+    return guarded([&] {
+        INRCT_REQUIRE(model && theta && u, "null argument");
+        INRCT_REQUIRE(model->arch.kind != INRCT_FFN || B, "FFN needs B");
+        model_eval_grid(model, theta, B, u, stream);
+    });
+}
+
+int inr_eval_points(inrct_model *model, const float *theta, const float *B, const int32_t *idx,
+                    int64_t k, float *f_out, hipStream_t stream) {
+    return guarded([&] {
+        INRCT_REQUIRE(model && theta && (k == 0 || (idx && f_out)), "null argument");
+        INRCT_REQUIRE(model->arch.kind != INRCT_FFN || B, "FFN needs B");
+        INRCT_REQUIRE(k >= 0, "k must be >= 0");
+        if (k > 0) model_eval_points(model, theta, B, idx, k, f_out, stream);
+    });
+}
+
+int inr_vjp_subsampled(inrct_model *model, const float *theta, const float *B,
+                       const int32_t *idx, int64_t k, const float *v, int v_compact,
+                       double scale, float *grad, hipStream_t stream) {
+    return guarded([&] {
+        INRCT_REQUIRE(model && theta && idx && v && grad, "null argument");
+        INRCT_REQUIRE(model->arch.kind != INRCT_FFN || B, "FFN needs B");
+        INRCT_REQUIRE(k >= 1 && k <= model->max_k, "k must be in [1, max_k=%lld]",
+                      (long long)model->max_k);
+        model_vjp(model, theta, B, idx, k, v, v_compact, scale, grad, stream);
+    });
+}
+
+}  // extern "C"

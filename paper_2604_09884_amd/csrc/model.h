@@ -1,0 +1,67 @@
+// Internal definition of the model handle (shared by mlp.hip and step.hip).
+#pragma once
+
+#include "common.h"
+
+struct inrct_model {
+    inr_arch arch;
+    int N = 0, dim = 0;
+    long long n_grid = 0, n_params = 0, n_fov = 0, max_k = 0;
+    inrct::FovHost fov;
+
+    // parameter offsets of each affine layer (1-based; L+1 = output layer)
+    std::vector<long long> loff;
+    inrct::DevBuf d_loff;
+
+    // packed MFMA A operands: forward (layers 1..L or 2..L) and transposed
+    // (layers 2..L); one record per fragment: layer, M-tile, k-step
+    long long nfrag = 0, nfragT = 0;
+    long long frag_off[10] = {0}, fragT_off[10] = {0};
+    inrct::DevBuf frag, fragT, pk_layer, pk_mt, pk_s;
+
+    // VJP chunk scratch
+    long long P_alloc = 0;       // points per chunk (row stride)
+    int kslice = 2048, nks = 0;  // split-K slice length and count
+    long long act_off[10] = {0}, sig_off[10] = {0};
+    long long act_elems = 0, dlt_elems = 0, sig_elems = 0;
+    inrct::DevBuf act, dlt, sig, part, tiles;
+    int ntiles = 0;
+
+    // sampler: FOV-rank membership bytes and per-block counts
+    inrct::DevBuf flags, blk;
+    long long n_blk = 0;
+
+    // Adam float64 partials
+    inrct::DevBuf apart;
+    int n_apart = 0;
+
+    bool bf16() const { return arch.mlp_dtype == INRCT_BF16; }
+};
+
+namespace inrct {
+// sampler / Adam / E helpers implemented in mlp.hip and step.hip
+void model_pack(inrct_model *m, const float *theta, hipStream_t s);
+void model_eval_grid(inrct_model *m, const float *theta, const float *B, float *u,
+                     hipStream_t s, bool pack = true);
+void model_zero_outside(inrct_model *m, float *u, hipStream_t s);
+void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u,
+                    hipStream_t s);
+void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t *idx,
+               long long k, const float *v, int v_compact, double scale, float *grad,
+               hipStream_t s, bool pack = true);
+void model_sample(inrct_model *m, uint64_t seed, uint64_t step, long long k, int32_t *idx,
+                  hipStream_t s);
+void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float *g,
+                long long t, double lr, double b1, double b2, double eps, double *gn2,
+                hipStream_t s);
+
+int64_t geom_rays(const inrct_geom *g);
+int geom_dim(const inrct_geom *g);
+int geom_N(const inrct_geom *g);
+void project(inrct_geom *geom, const float *u, float *z, hipStream_t s);
+void backproject(inrct_geom *geom, const float *r, float *v, hipStream_t s);
+void backproject_at(inrct_geom *geom, const float *r, const int32_t *idx, int64_t k,
+                    float *out, hipStream_t s);
+void residual_loss(inrct_geom *geom, int loss, const float *z, const float *y, float *r,
+                   double *loss_out, hipStream_t s);
+}  // namespace inrct

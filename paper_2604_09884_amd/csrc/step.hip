@@ -1,0 +1,384 @@
+// Index sampler, Adam, and Algorithm 1 + Adam on a context.
+//
+// Sampler: the first k images of a keyed pseudo-random permutation of the
+// FOV ranks (a uniform k-subset without replacement, so Eq. (2) is
+// unbiased).  Marks are written into a byte per FOV rank -- each rank is
+// hit by exactly one thread because the map is a bijection -- and compacted
+// in rank order with a fixed-order scan, giving sorted grid indices.
+#include <math.h>
+
+#include "model.h"
+
+namespace inrct {
+
+// --------------------------------------------------------------- sampler
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+struct PrpKey {
+    unsigned long long k[6];
+    int hb;
+    unsigned long long n;
+};
+
+static PrpKey make_key(uint64_t seed, uint64_t step, long long n) {
+    auto hmix = [](unsigned long long z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    };
+    PrpKey key;
+    int b = 2;
+    while ((1ULL << b) < (unsigned long long)n) ++b;
+    key.hb = (b + 1) / 2;
+    key.n = (unsigned long long)n;
+    for (int r = 0; r < 6; ++r)
+        key.k[r] = hmix(seed ^ hmix(step ^ (0x9E3779B97F4A7C15ULL * (unsigned long long)(r + 1))));
+    return key;
+}
+
+__device__ __forceinline__ unsigned long long feistel(unsigned long long x, const PrpKey &key) {
+    const int hb = key.hb;
+    const unsigned long long mask = (1ULL << hb) - 1;
+    unsigned long long L = x >> hb, R = x & mask;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const unsigned long long t = L ^ (mix64(key.k[r] ^ R) >> (64 - hb));
+        L = R;
+        R = t;
+    }
+    return (L << hb) | R;
+}
+
+// flags[pi(j)] = 1 for j < k.  Cycle walking ends because the orbit of j
+// under the bijection returns to j < n; the bound is a guard only.
+__global__ void k_mark(PrpKey key, long long k, unsigned char *__restrict__ flags,
+                       int *__restrict__ overflow) {
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (j >= k) return;
+    unsigned long long y = feistel((unsigned long long)j, key);
+    const unsigned long long dom = 1ULL << (2 * key.hb);
+    unsigned long long it = 0;
+    while (y >= key.n && it < dom) {
+        y = feistel(y, key);
+        ++it;
+    }
+    if (y < key.n) flags[y] = 1;
+    else overflow[0] = 1;
+}
+
+// per-block counts of set flags (4096 flags per block, 256 threads x 16)
+__global__ __launch_bounds__(256) void k_count(const unsigned char *__restrict__ flags,
+                                               long long n, long long *__restrict__ blk) {
+    __shared__ int sh[256];
+    const long long base = (long long)blockIdx.x * 4096 + threadIdx.x * 16;
+    int c = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < n) c += flags[base + i];
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of the block counts, in place (single block of 1024)
+__global__ __launch_bounds__(1024) void k_scan(long long *__restrict__ blk, long long nb) {
+    __shared__ long long sh[1024];
+    const int t = threadIdx.x;
+    const long long per = (nb + 1023) / 1024;
+    const long long lo = t * per, hi = lo + per < nb ? lo + per : nb;
+    long long s = 0;
+    for (long long i = lo; i < hi; ++i) s += blk[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele
+        long long v = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    long long run = sh[t] - s;
+    for (long long i = lo; i < hi; ++i) {
+        const long long c = blk[i];
+        blk[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit(const unsigned char *__restrict__ flags, long long n,
+                                              const long long *__restrict__ blk, FovDev fov,
+                                              int32_t *__restrict__ out) {
+    __shared__ int sh[256];
+    const long long base = (long long)blockIdx.x * 4096 + threadIdx.x * 16;
+    int c = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < n) c += flags[base + i];
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    long long pos = blk[blockIdx.x] + sh[threadIdx.x] - c;
+    for (int i = 0; i < 16; ++i) {
+        const long long q = base + i;
+        if (q < n && flags[q]) {
+            int x, y, z;
+            out[pos++] = (int32_t)fov_rank_to_index(fov, q, &x, &y, &z);
+        }
+    }
+}
+
+void model_sample(inrct_model *m, uint64_t seed, uint64_t step, long long k, int32_t *idx,
+                  hipStream_t s) {
+    const long long n = m->n_fov;
+    const PrpKey key = make_key(seed, step, n);
+    launch_zero_bytes(m->flags.ptr, (size_t)n, s);
+    // the overflow word lives after the block counts (never set in practice)
+    hipLaunchKernelGGL(k_mark, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, key, k,
+                       m->flags.as<unsigned char>(),
+                       (int *)(m->blk.as<long long>() + m->n_blk));
+    INRCT_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_count, dim3((unsigned)m->n_blk), dim3(256), 0, s,
+                       m->flags.as<unsigned char>(), n, m->blk.as<long long>());
+    INRCT_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, m->blk.as<long long>(), m->n_blk);
+    INRCT_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)m->n_blk), dim3(256), 0, s,
+                       m->flags.as<unsigned char>(), n, m->blk.as<long long>(),
+                       m->fov.dev(m->dim), idx);
+    INRCT_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------------ Adam
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ th, float *__restrict__ mm,
+                                              float *__restrict__ vv, const float *__restrict__ g,
+                                              long long p, float b1, float b2, float step_size,
+                                              float inv_sqrt_bc2, float eps,
+                                              double *__restrict__ partials) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < p; i += stride) {
+        const float gi = g[i];
+        const float mi = b1 * mm[i] + (1.f - b1) * gi;
+        const float vi = b2 * vv[i] + (1.f - b2) * gi * gi;
+        mm[i] = mi;
+        vv[i] = vi;
+        th[i] -= step_size * mi / (sqrtf(vi) * inv_sqrt_bc2 + eps);
+        acc += (double)gi * (double)gi;
+    }
+    const double s = block_sum_f64(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float *g, long long t,
+                double lr, double b1, double b2, double eps, double *gn2, hipStream_t s) {
+    const double bc1 = 1.0 - pow(b1, (double)t);
+    const double bc2 = 1.0 - pow(b2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3(m->n_apart), dim3(256), 0, s, theta, mm, vv, g, m->n_params,
+                       (float)b1, (float)b2, (float)(lr / bc1), (float)(1.0 / sqrt(bc2)),
+                       (float)eps, m->apart.as<double>());
+    INRCT_CHECK_LAUNCH();
+    if (gn2) launch_sum_partials(m->apart.as<double>(), m->n_apart, gn2, s);
+}
+
+}  // namespace inrct
+
+// ==================================================================== ABI
+using namespace inrct;
+
+struct inr_ctx {
+    inrct_model *model = nullptr;
+    inrct_geom *geom = nullptr;
+    inrct_step_cfg cfg;
+    float *theta = nullptr, *am = nullptr, *av = nullptr;
+    const float *B = nullptr, *y = nullptr;
+    DevBuf u, r, v, g, idx;
+    // optional stage timing: events[slot][stage][0=start, 1=end]
+    std::vector<hipEvent_t> events;
+    int t_slots = 0, t_used = 0;
+    ~inr_ctx() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+    hipEvent_t ev(int stage, int end) const {
+        const int slot = t_used % t_slots;
+        return events[((size_t)slot * kStages + stage) * 2 + end];
+    }
+    static const int kStages = 8;
+};
+
+extern "C" {
+
+int inrct_sample(inrct_model *model, uint64_t seed, uint64_t step, int64_t k, int32_t *idx_out,
+                 hipStream_t stream) {
+    return guarded([&] {
+        INRCT_REQUIRE(model && idx_out, "null argument");
+        INRCT_REQUIRE(k >= 1 && k <= model->max_k, "k must be in [1, max_k=%lld]",
+                      (long long)model->max_k);
+        model_sample(model, seed, step, k, idx_out, stream);
+    });
+}
+
+int inrct_adam(inrct_model *model, float *theta, float *m, float *v, const float *g, int64_t t,
+               double lr, double beta1, double beta2, double eps, double *gnorm2_out,
+               hipStream_t stream) {
+    return guarded([&] {
+        INRCT_REQUIRE(model && theta && m && v && g, "null argument");
+        INRCT_REQUIRE(t >= 1, "t is 1-based");
+        INRCT_REQUIRE(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && lr > 0,
+                      "bad Adam hyper-parameters");
+        model_adam(model, theta, m, v, g, t, lr, beta1, beta2, eps, gnorm2_out, stream);
+    });
+}
+
+int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *cfg, float *theta,
+                   float *adam_m, float *adam_v, const float *B, const float *y, inr_ctx **out) {
+    return guarded([&] {
+        INRCT_REQUIRE(model && geom && cfg && theta && adam_m && adam_v && y && out,
+                      "null argument");
+        *out = nullptr;
+        INRCT_REQUIRE(geom_dim(geom) == model->dim && geom_N(geom) == model->N,
+                      "model grid and geometry grid differ");
+        INRCT_REQUIRE(model->arch.kind != INRCT_FFN || B, "FFN needs B");
+        INRCT_REQUIRE(cfg->k >= 1 && cfg->k <= model->max_k, "k must be in [1, max_k]");
+        INRCT_REQUIRE(cfg->loss == INRCT_LS || cfg->loss == INRCT_FLS, "unknown loss");
+        INRCT_REQUIRE(cfg->v_mode == INRCT_V_FULL || cfg->v_mode == INRCT_V_AT_I,
+                      "unknown v_mode");
+        INRCT_REQUIRE(cfg->lr > 0 && cfg->eps > 0 && cfg->beta1 >= 0 && cfg->beta1 < 1 &&
+                          cfg->beta2 >= 0 && cfg->beta2 < 1,
+                      "bad Adam hyper-parameters");
+        inr_ctx *c = new inr_ctx();
+        try {
+            c->model = model;
+            c->geom = geom;
+            c->cfg = *cfg;
+            c->theta = theta;
+            c->am = adam_m;
+            c->av = adam_v;
+            c->B = B;
+            c->y = y;
+            c->u.alloc(sizeof(float) * model->n_grid);
+            c->r.alloc(sizeof(float) * geom_rays(geom));
+            c->v.alloc(sizeof(float) * (cfg->v_mode == INRCT_V_FULL ? model->n_grid : cfg->k));
+            c->g.alloc(sizeof(float) * model->n_params);
+            c->idx.alloc(sizeof(int32_t) * cfg->k);
+        } catch (...) {
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+int inr_ctx_destroy(inr_ctx *ctx) {
+    delete ctx;
+    return INRCT_OK;
+}
+
+void *inr_ctx_buffer(inr_ctx *ctx, int which) {
+    if (!ctx) return nullptr;
+    switch (which) {
+        case 0: return ctx->u.ptr;
+        case 1: return ctx->r.ptr;
+        case 2: return ctx->v.ptr;
+        case 3: return ctx->g.ptr;
+        case 4: return ctx->idx.ptr;
+        default: return nullptr;
+    }
+}
+
+int inr_ctx_enable_timing(inr_ctx *c, int max_steps) {
+    return guarded([&] {
+        INRCT_REQUIRE(c && max_steps >= 1 && max_steps <= 100000, "bad arguments");
+        for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+        c->events.assign((size_t)max_steps * inr_ctx::kStages * 2, nullptr);
+        for (auto &e : c->events) INRCT_CHECK_HIP(hipEventCreate(&e));
+        c->t_slots = max_steps;
+        c->t_used = 0;
+    });
+}
+
+int inr_ctx_stage_ms(inr_ctx *c, int n_stages, double *ms_out) {
+    return guarded([&] {
+        INRCT_REQUIRE(c && ms_out && n_stages >= 1 && n_stages <= inr_ctx::kStages,
+                      "bad arguments");
+        INRCT_REQUIRE(c->t_slots > 0, "timing not enabled");
+        const int steps = std::min(c->t_used, c->t_slots);
+        for (int st = 0; st < n_stages; ++st) {
+            double tot = 0.0;
+            for (int k = 0; k < steps; ++k) {
+                float ms = 0.f;
+                hipEvent_t a = c->events[((size_t)k * inr_ctx::kStages + st) * 2];
+                hipEvent_t b = c->events[((size_t)k * inr_ctx::kStages + st) * 2 + 1];
+                INRCT_CHECK_HIP(hipEventSynchronize(b));
+                INRCT_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+                tot += ms;
+            }
+            ms_out[st] = tot;
+        }
+        c->t_used = 0;
+    });
+}
+
+int inr_grad_step(inr_ctx *c, uint64_t step, double *loss_out, double *gnorm2_out,
+                  hipStream_t s) {
+    return guarded([&] {
+        INRCT_REQUIRE(c, "null context");
+        const bool timed = c->t_slots > 0;
+        auto mark = [&](int stage, int end) {
+            if (timed) INRCT_CHECK_HIP(hipEventRecord(c->ev(stage, end), s));
+        };
+        inrct_model *m = c->model;
+        const long long k = c->cfg.k;
+        float *u = c->u.as<float>(), *r = c->r.as<float>(), *v = c->v.as<float>();
+        int32_t *idx = c->idx.as<int32_t>();
+        mark(7, 0);
+        // Algorithm 1, step 1: z = P E{f_theta}
+        model_pack(m, c->theta, s);
+        model_zero_outside(m, u, s);
+        mark(0, 0);
+        model_eval_fov(m, c->theta, c->B, u, s);
+        mark(0, 1);
+        mark(1, 0);
+        project(c->geom, u, r, s);
+        mark(1, 1);
+        // step 2: r = dL/dz, v = P^T r
+        mark(2, 0);
+        residual_loss(c->geom, c->cfg.loss, r, c->y, r, loss_out, s);
+        mark(2, 1);
+        // step 3: the index set I
+        mark(3, 0);
+        model_sample(m, c->cfg.seed, step, k, idx, s);
+        mark(3, 1);
+        mark(4, 0);
+        if (c->cfg.v_mode == INRCT_V_FULL) {
+            backproject(c->geom, r, v, s);
+        } else {
+            backproject_at(c->geom, r, idx, k, v, s);
+        }
+        mark(4, 1);
+        // steps 4-5: gradient of the virtual loss, Eq. (2)/(3)
+        const double scale = (double)m->n_fov / (double)k;
+        mark(5, 0);
+        model_vjp(m, c->theta, c->B, idx, k, v, c->cfg.v_mode == INRCT_V_AT_I ? 1 : 0, scale,
+                  c->g.as<float>(), s, false);
+        mark(5, 1);
+        mark(6, 0);
+        model_adam(m, c->theta, c->am, c->av, c->g.as<float>(), (long long)step + 1, c->cfg.lr,
+                   c->cfg.beta1, c->cfg.beta2, c->cfg.eps, gnorm2_out, s);
+        mark(6, 1);
+        mark(7, 1);
+        if (timed) ++c->t_used;
+    });
+}
+
+}  // extern "C"

@@ -15,6 +15,7 @@ Ray conventions are those stated in ``configs``.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -194,10 +195,16 @@ def rays(problem: Problem, views=None):
 def sinogram(problem: Problem, ph=None, noisy: bool = True) -> np.ndarray:
     """Measured data y, FP64, shape [V][K] (2D) or [V][Nv][Nu] (3D)."""
     ph = phantom(problem) if ph is None else ph
-    out = []
-    for j in range(problem.n_views):
+
+    def one(j):
         p0, d = rays(problem, views=[j])
-        out.append(chord_integrals(ph, problem.dim, p0, d))
+        return chord_integrals(ph, problem.dim, p0, d)
+    if problem.n_rays > 200000:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(16, os.cpu_count() or 4)) as ex:
+            out = list(ex.map(one, range(problem.n_views)))
+    else:
+        out = [one(j) for j in range(problem.n_views)]
     y = np.concatenate(out)
     if noisy and problem.photons > 0:
         rng = np.random.default_rng(problem.seed_noise)

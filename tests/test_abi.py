@@ -1,0 +1,42 @@
+"""The C ABI library loads and exports every function inrct.h declares
+(no compute; runs without a GPU)."""
+import ctypes
+import os
+import re
+
+from paper_2604_09884_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "inrct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_five_named_calls():
+    names = _declared()
+    for n in ("inr_eval_grid", "ct_project", "ct_backproject", "inr_vjp_subsampled",
+              "inr_grad_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2604_09884_amd import build
+        build.build()
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(L.EXPORTED) == sorted(_declared())
+
+
+def test_errors_are_reported_without_a_gpu():
+    lib = L.load()
+    h = ctypes.c_void_p()
+    grid = L.InrGrid(2, 0)
+    a = L.InrArch(1, 2, 8, 128, 2, 30.0, 0)
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
+    assert rc == -1
+    assert b"grid n" in lib.inrct_last_error()
