@@ -123,7 +123,9 @@ __global__ void k_pack(MlpDev m, const float *__restrict__ theta, int bf, void *
     if (!trans) {
         const int o = 32 * mt + i;
         const int KS = ksteps(K, bf ? 16 : 2);
-        if (s == KS - 1) {
+        if (s >= KS) {
+            val = 0.f;  // padding k-step
+        } else if (s == KS - 1) {
             val = (h == 0 && p == 0) ? bl[o] : 0.f;
         } else {
             const int col = (l == 1) ? enc_feature(bf, m.F, s, h, p) : chain_feature(bf, s, h, p);
@@ -244,14 +246,14 @@ __device__ __forceinline__ void mlp_forward(const MlpDev &m, const float (&xc)[N
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const Op a = fr[((long long)mt * KS + s) * 64 + lane];
+                const Op a = fr[((long long)s * MT + mt) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, bop[nt], acc[nt][mt]);
             }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const Op a = fr[((long long)mt * KS + KS - 1) * 64 + lane];
+            const Op a = fr[((long long)(KS - 1) * MT + mt) * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, one_b, acc[nt][mt]);
         }
@@ -326,11 +328,11 @@ __device__ __forceinline__ void mlp_forward(const MlpDev &m, const float (&xc)[N
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const Op a = fr[((long long)mt * KS + s) * 64 + lane];
+                const Op a = fr[((long long)s * MT + mt) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, bin[nt][s], acc[nt][mt]);
             }
-            const Op a = fr[((long long)mt * KS + NS) * 64 + lane];
+            const Op a = fr[((long long)NS * MT + mt) * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, one_b, acc[nt][mt]);
         }
@@ -441,6 +443,442 @@ __global__ __launch_bounds__(256) void k_eval_points(MlpDev m, const int32_t *__
         if (lane < 32 && j[nt] < k) out[j[nt]] = f[nt];
 }
 
+// ---------------------------------------- E with LDS-staged weights (BF16)
+// Persistent workgroups of four waves; a workgroup tile is 256 consecutive
+// FOV ranks and each wave evaluates 64 of them (two 32-point N-tiles, so
+// every A fragment read from LDS feeds two MFMAs).  The packed weights are
+// one stream of "chunks" (one k-step of one layer: MT fragments of 1 KB,
+// s-major), copied global -> LDS with direct-to-LDS loads kRingD chunks
+// ahead into a ring of kRingD + 1 slots.  At each chunk boundary a wave
+// waits until only its own later copies are outstanding, then the
+// workgroup barrier makes the chunk visible and frees the slot the next
+// copy overwrites.  The Fourier encoding uses the hardware sine/cosine on
+// the fractional phase (turns), adequate for BF16 operands.
+constexpr int kRingD = 6;
+constexpr int kRingNB = kRingD + 1;
+
+// 16-byte-per-lane copy global -> LDS (lane i lands at base + 16 i).  Issued
+// from inline assembly: the compiler would otherwise assume every later LDS
+// read may alias the copy and wait for all vector memory before it; here the
+// ring protocol (explicit vmcnt wait + barrier) orders the accesses.  The
+// instruction has no destination register; its address operand is read at
+// issue.
+__device__ __forceinline__ void dma16(const void *g, void *lds_wave_base) {
+    const unsigned lds = (unsigned)(size_t)(__attribute__((address_space(3))) void *)lds_wave_base;
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(g)
+                 : "memory", "m0");
+}
+
+template <int W>
+struct RingCfg {
+    static constexpr int MT = W / 32;
+    static constexpr int PER_WAVE = MT / 4;           // fragment copies per wave per chunk
+    static constexpr int CHUNK = MT * 1024;           // bytes
+};
+
+template <int W>
+__device__ __forceinline__ void ring_issue(const char *__restrict__ gfrag, int chunk_src,
+                                           char *ring, int slot, int wave, int lane) {
+    typedef RingCfg<W> RC;
+#pragma unroll
+    for (int i = 0; i < RC::PER_WAVE; ++i) {
+        const int f = wave * RC::PER_WAVE + i;
+        const char *src = gfrag + ((size_t)chunk_src * RC::MT + f) * 1024 + lane * 16;
+        dma16(src, ring + slot * RC::CHUNK + f * 1024);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void ring_wait() {
+    // all but this wave's copies of the next kRingD - 1 chunks have landed
+    if constexpr (RingCfg<W>::PER_WAVE == 2) asm volatile("s_waitcnt vmcnt(10)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_bf(float z, float w0) {
+    if constexpr (ACT == INRCT_FFN) return fmaxf(z, 0.f);
+    else return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(w0 * z * 0.15915494309189535f));
+}
+
+template <int W, int ACT>
+__global__ __launch_bounds__(256) void k_eval_lds(MlpDev m, int n, int ntiles, int nchunks,
+                                                   float *__restrict__ u) {
+    typedef RingCfg<W> RC;
+    constexpr int MT = RC::MT;
+    constexpr int NT = 2;
+    constexpr int NS = W / 16;
+    __shared__ __attribute__((aligned(16))) char ring[kRingNB * RC::CHUNK];
+    __shared__ float sB[3 * 512];
+    __shared__ float sWout[W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+    const char *gfrag = (const char *)m.frag;
+    // constants to LDS
+    if constexpr (ACT == INRCT_FFN) {
+        for (int i = threadIdx.x; i < m.F * m.d; i += 256) sB[i] = m.B[i];
+    }
+    for (int i = threadIdx.x; i < W; i += 256) sWout[i] = m.w_out[i];
+    const float b_out = m.b_out[0];
+    bf16x8 one_b;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) one_b[p] = (__bf16)((h == 0 && p == 0) ? 1.f : 0.f);
+
+    // ring state: slot being consumed, slot and source of the next copy
+    int slot = 0, fill_slot = kRingD % kRingNB, fill_src = kRingD % nchunks;
+#pragma unroll
+    for (int i = 0; i < kRingD; ++i) ring_issue<W>(gfrag, i % nchunks, ring, i, wave, lane);
+
+    auto next_chunk = [&]() -> const bf16x8 * {
+        ring_wait<W>();
+        __syncthreads();
+        ring_issue<W>(gfrag, fill_src, ring, fill_slot, wave, lane);
+        fill_src = fill_src + 1 == nchunks ? 0 : fill_src + 1;
+        fill_slot = fill_slot + 1 == kRingNB ? 0 : fill_slot + 1;
+        const bf16x8 *p = (const bf16x8 *)(ring + slot * RC::CHUNK);
+        slot = slot + 1 == kRingNB ? 0 : slot + 1;
+        return p;
+    };
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        float xc[NT][3];
+        int gidx[NT];
+        const int base = tile * 256 + wave * 64;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            int q = base + nt * 32 + (lane & 31);
+            const bool ok = q < n;
+            if (!ok) q = n - 1;
+            int ix, iy, iz;
+            gidx[nt] = (int)fov_rank_to_index(m.fov, q, &ix, &iy, &iz);
+            if (!ok) gidx[nt] = -1;
+            xc[nt][0] = grid_coord(ix, m.fov.N);
+            xc[nt][1] = grid_coord(iy, m.fov.N);
+            xc[nt][2] = m.fov.dim == 3 ? grid_coord(iz, m.fov.N) : 0.f;
+        }
+        f32x16 acc[NT][MT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
+        // ---------------- layer 1
+        if constexpr (ACT == INRCT_FFN) {
+            const int KS1 = m.F / 8;  // k-steps without the bias step
+            for (int s = 0; s < KS1; ++s) {
+                bf16x8 b[NT];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int f = 8 * s + 4 * h + q;
+                    const float bx = sB[f * m.d], by = sB[f * m.d + 1];
+                    const float bz = m.d == 3 ? sB[f * m.d + 2] : 0.f;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const float t = fmaf(bz, xc[nt][2], fmaf(by, xc[nt][1], bx * xc[nt][0]));
+                        const float r = __builtin_amdgcn_fractf(t);
+                        b[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
+                        b[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
+                    }
+                }
+                const bf16x8 *A = next_chunk();
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const bf16x8 a = A[mt * 64 + lane];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[nt], acc[nt][mt], 0, 0, 0);
+                }
+            }
+            const bf16x8 *A = next_chunk();
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const bf16x8 a = A[mt * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, one_b, acc[nt][mt], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int o = 32 * mt + crow(r, h);
+                    const float w0 = m.W1[o * m.d], w1 = m.W1[o * m.d + 1];
+                    const float w2 = m.d == 3 ? m.W1[o * m.d + 2] : 0.f;
+                    const float bb = m.b1[o];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[nt][mt][r] = fmaf(w2, xc[nt][2], fmaf(w1, xc[nt][1], fmaf(w0, xc[nt][0], bb)));
+                }
+        }
+        // ---------------- layers 2..L
+        for (int l = 2; l <= m.L; ++l) {
+            bf16x8 bin[NT][NS];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int p = 0; p < 8; ++p)
+                        bin[nt][s][p] = (__bf16)act_bf<ACT>(acc[nt][s / 2][8 * (s % 2) + p], m.omega0);
+#pragma unroll
+            for (int s = 0; s <= NS; ++s) {
+                const bf16x8 *A = next_chunk();
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const bf16x8 a = A[mt * 64 + lane];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            a, s < NS ? bin[nt][s] : one_b, s == 0 ? (f32x16){0} : acc[nt][mt],
+                            0, 0, 0);
+                }
+            }
+        }
+        // ---------------- output layer
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            float sacc = 0.f;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    sacc = fmaf(sWout[32 * mt + crow(r, h)], act_bf<ACT>(acc[nt][mt][r], m.omega0), sacc);
+            sacc += __shfl_xor(sacc, 32);
+            if (lane < 32 && gidx[nt] >= 0) u[gidx[nt]] = sacc + b_out;
+        }
+        // keep the copy counter exact: drain stores and copies in flight
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Width-256 variant: hidden layers produce their 256 outputs in two halves
+// of four M-tiles, so only half the accumulators are live next to the
+// layer's inputs; a hidden-layer chunk is two k-steps x four M-tiles (the
+// 18th k-step of each half is padding and is not computed).  Layer 1 keeps
+// all eight M-tiles live (its B operands are generated per k-step).
+struct RingState {
+    char *ring;
+    const char *gfrag;
+    int slot, fill_slot, fill_src, nchunks, wave, lane;
+    __device__ __forceinline__ const bf16x8 *next() {
+        ring_wait<256>();
+        __syncthreads();
+        ring_issue<256>(gfrag, fill_src, ring, fill_slot, wave, lane);
+        fill_src = fill_src + 1 == nchunks ? 0 : fill_src + 1;
+        fill_slot = fill_slot + 1 == kRingNB ? 0 : fill_slot + 1;
+        const bf16x8 *p = (const bf16x8 *)(ring + slot * RingCfg<256>::CHUNK);
+        slot = slot + 1 == kRingNB ? 0 : slot + 1;
+        return p;
+    }
+};
+
+// One half (four M-tiles) of a width-256 hidden layer: acc = W_half [bin; 1].
+template <int HALF>
+__device__ __forceinline__ void half_gemm(RingState &rs, const bf16x8 (&bin)[2][16],
+                                          const bf16x8 &one_b, f32x16 (&acc)[2][4], int lane) {
+#pragma unroll
+    for (int pair = 0; pair <= 8; ++pair) {
+        const bf16x8 *A = rs.next();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int s = 2 * pair + j;
+            if (s > 16) continue;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const bf16x8 a = A[(j * 4 + mt) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        a, s < 16 ? bin[nt][s] : one_b, s == 0 ? (f32x16){0} : acc[nt][mt], 0, 0,
+                        0);
+            }
+        }
+    }
+}
+
+template <int ACT, int HALF>
+__device__ __forceinline__ void half_to_b(const f32x16 (&acc)[2][4], bf16x8 (&out)[2][8],
+                                          float w0) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int so = 0; so < 8; ++so)
+#pragma unroll
+            for (int p = 0; p < 8; ++p)
+                out[nt][so][p] = (__bf16)act_bf<ACT>(acc[nt][so / 2][8 * (so % 2) + p], w0);
+}
+
+template <int ACT, int HALF>
+__device__ __forceinline__ void half_out(const f32x16 (&acc)[2][4], const float *sWout, int h,
+                                         float (&fout)[2], float w0) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                fout[nt] = fmaf(sWout[32 * (HALF * 4 + mt) + crow(r, h)],
+                                act_bf<ACT>(acc[nt][mt][r], w0), fout[nt]);
+}
+
+template <int ACT>
+__global__ __launch_bounds__(256) void k_eval_lds_h(MlpDev m, int n, int ntiles, int nchunks,
+                                                    const char *__restrict__ gfrag,
+                                                    float *__restrict__ u) {
+    constexpr int MT = 8, NT = 2, NS = 16;
+    __shared__ __attribute__((aligned(16))) char ring[kRingNB * RingCfg<256>::CHUNK];
+    __shared__ float sB[3 * 512];
+    __shared__ float sWout[256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+    if constexpr (ACT == INRCT_FFN) {
+        for (int i = threadIdx.x; i < m.F * m.d; i += 256) sB[i] = m.B[i];
+    }
+    for (int i = threadIdx.x; i < 256; i += 256) sWout[i] = m.w_out[i];
+    const float b_out = m.b_out[0];
+    const float w0 = m.omega0;
+    bf16x8 one_b;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) one_b[p] = (__bf16)((h == 0 && p == 0) ? 1.f : 0.f);
+
+    RingState rs{ring, gfrag, 0, kRingD % kRingNB, kRingD % nchunks, nchunks, wave, lane};
+#pragma unroll
+    for (int i = 0; i < kRingD; ++i) ring_issue<256>(gfrag, i % nchunks, ring, i, wave, lane);
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        float xc[NT][3];
+        int gidx[NT];
+        const int base = tile * 256 + wave * 64;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            int q = base + nt * 32 + (lane & 31);
+            const bool ok = q < n;
+            if (!ok) q = n - 1;
+            int ix, iy, iz;
+            gidx[nt] = (int)fov_rank_to_index(m.fov, q, &ix, &iy, &iz);
+            if (!ok) gidx[nt] = -1;
+            xc[nt][0] = grid_coord(ix, m.fov.N);
+            xc[nt][1] = grid_coord(iy, m.fov.N);
+            xc[nt][2] = m.fov.dim == 3 ? grid_coord(iz, m.fov.N) : 0.f;
+        }
+        bf16x8 bin[NT][NS];
+        {
+            // ---------------- layer 1, all eight M-tiles
+            f32x16 acc[NT][MT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
+            if constexpr (ACT == INRCT_FFN) {
+                const int KS1 = m.F / 8;
+                for (int s = 0; s <= KS1; ++s) {
+                    bf16x8 b[NT];
+                    if (s < KS1) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int f = 8 * s + 4 * h + q;
+                            const float bx = sB[f * m.d], by = sB[f * m.d + 1];
+                            const float bz = m.d == 3 ? sB[f * m.d + 2] : 0.f;
+#pragma unroll
+                            for (int nt = 0; nt < NT; ++nt) {
+                                const float t = fmaf(bz, xc[nt][2], fmaf(by, xc[nt][1], bx * xc[nt][0]));
+                                const float r = __builtin_amdgcn_fractf(t);
+                                b[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
+                                b[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) b[nt] = one_b;
+                    }
+                    const bf16x8 *A = rs.next();
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const bf16x8 a = A[mt * 64 + lane];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                a, b[nt], acc[nt][mt], 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int o = 32 * mt + crow(r, h);
+                        const float c0 = m.W1[o * m.d], c1 = m.W1[o * m.d + 1];
+                        const float c2 = m.d == 3 ? m.W1[o * m.d + 2] : 0.f;
+                        const float bb = m.b1[o];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[nt][mt][r] = fmaf(c2, xc[nt][2], fmaf(c1, xc[nt][1], fmaf(c0, xc[nt][0], bb)));
+                    }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int p = 0; p < 8; ++p)
+                        bin[nt][s][p] = (__bf16)act_bf<ACT>(acc[nt][s / 2][8 * (s % 2) + p], w0);
+        }
+        // ---------------- layers 2..L-1: two halves each
+        for (int l = 2; l < m.L; ++l) {
+            bf16x8 lo[NT][8], hi[NT][8];
+            {
+                f32x16 acc[NT][4];
+                half_gemm<0>(rs, bin, one_b, acc, lane);
+                half_to_b<ACT, 0>(acc, lo, w0);
+            }
+            {
+                f32x16 acc[NT][4];
+                half_gemm<1>(rs, bin, one_b, acc, lane);
+                half_to_b<ACT, 1>(acc, hi, w0);
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) {
+                    bin[nt][s2] = lo[nt][s2];
+                    bin[nt][8 + s2] = hi[nt][s2];
+                }
+        }
+        // ---------------- last hidden layer L and the linear output
+        float fout[NT] = {0.f, 0.f};
+        if (m.L >= 2) {
+            {
+                f32x16 acc[NT][4];
+                half_gemm<0>(rs, bin, one_b, acc, lane);
+                half_out<ACT, 0>(acc, sWout, h, fout, w0);
+            }
+            {
+                f32x16 acc[NT][4];
+                half_gemm<1>(rs, bin, one_b, acc, lane);
+                half_out<ACT, 1>(acc, sWout, h, fout, w0);
+            }
+        } else {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+                    for (int p = 0; p < 8; ++p) {
+                        const int r = 8 * (s2 % 2) + p;
+                        fout[nt] = fmaf(sWout[32 * (s2 / 2) + crow(r, h)], (float)bin[nt][s2][p], fout[nt]);
+                    }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float sacc = fout[nt] + __shfl_xor(fout[nt], 32);
+            if (lane < 32 && gidx[nt] >= 0) u[gidx[nt]] = sacc + b_out;
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // ------------------------------------------------ VJP phase 1: fwd + deltas
 // Points j0 .. j0 + P of the index list form the chunk; column c of the
 // scratch holds point j0 + c (columns past k carry a zero cotangent).
@@ -521,7 +959,7 @@ __global__ __launch_bounds__(256) void k_vjp_tile(MlpDev m, const int32_t *__res
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const Op a = fr[((long long)mt * NS + s) * 64 + lane];
+                const Op a = fr[((long long)s * MT + mt) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = PR::mma(a, bin[nt][s], acc[nt][mt]);
             }
@@ -680,6 +1118,13 @@ void model_pack(inrct_model *m, const float *theta, hipStream_t s) {
                        m->d_loff.as<long long>(), m->pk_layer.as<int>(), m->pk_mt.as<int>(),
                        m->pk_s.as<int>());
     INRCT_CHECK_LAUNCH();
+    if (m->nfrag_h > 0) {
+        const long long th = m->nfrag_h * 64 * 8;
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)cdiv(th, 256)), dim3(256), 0, s, d, theta, 1,
+                           m->frag_h.ptr, nullptr, m->nfrag_h, 0LL, m->d_loff.as<long long>(),
+                           m->pkh_layer.as<int>(), m->pkh_mt.as<int>(), m->pkh_s.as<int>());
+        INRCT_CHECK_LAUNCH();
+    }
 }
 
 template <int W, int NT, bool BF, int ACT>
@@ -722,9 +1167,44 @@ void model_zero_outside(inrct_model *m, float *u, hipStream_t s) {
     INRCT_CHECK_LAUNCH();
 }
 
+template <int W, int ACT>
+static void launch_eval_lds(const inrct_model *m, const MlpDev &d, float *u, hipStream_t s) {
+    const long long ntiles = cdiv(m->n_fov, 256);
+    long long nchunks = 0;
+    const int l_first = m->arch.kind == INRCT_FFN ? 1 : 2;
+    for (int l = l_first; l <= m->arch.depth; ++l)
+        nchunks += ksteps(layer_K(m->arch.kind, m->arch.n_freq, m->arch.in_dim, W, l), 16);
+    const long long grid = std::min<long long>(ntiles, m->n_cu);
+    hipLaunchKernelGGL((k_eval_lds<W, ACT>), dim3((unsigned)grid), dim3(256), 0, s, d,
+                       (int)m->n_fov, (int)ntiles, (int)nchunks, u);
+    INRCT_CHECK_LAUNCH();
+}
+
 void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u,
                     hipStream_t s) {
     const MlpDev d = make_dev(m, theta, B);
+    const bool lds_path = m->bf16() && (m->arch.kind != INRCT_FFN || m->arch.n_freq <= 512) &&
+                          (m->arch.kind == INRCT_FFN || m->arch.depth >= 2);
+    if (lds_path) {
+        if (m->arch.width == 256) {
+            const long long ntiles = cdiv(m->n_fov, 256);
+            const long long grid = std::min<long long>(ntiles, m->n_cu);
+            const int nchunks = (int)(m->nfrag_h / 8);
+            if (m->arch.kind == INRCT_FFN)
+                hipLaunchKernelGGL(k_eval_lds_h<INRCT_FFN>, dim3((unsigned)grid), dim3(256), 0, s,
+                                   d, (int)m->n_fov, (int)ntiles, nchunks,
+                                   (const char *)m->frag_h.ptr, u);
+            else
+                hipLaunchKernelGGL(k_eval_lds_h<INRCT_SIREN>, dim3((unsigned)grid), dim3(256), 0,
+                                   s, d, (int)m->n_fov, (int)ntiles, nchunks,
+                                   (const char *)m->frag_h.ptr, u);
+            INRCT_CHECK_LAUNCH();
+        } else {
+            if (m->arch.kind == INRCT_FFN) launch_eval_lds<128, INRCT_FFN>(m, d, u, s);
+            else launch_eval_lds<128, INRCT_SIREN>(m, d, u, s);
+        }
+        return;
+    }
     INRCT_DISPATCH_W_BF(m, launch_eval_grid, d, m->n_fov, u, s);
 }
 
@@ -818,6 +1298,12 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             for (int i = 0; i < m->dim; ++i) m->n_grid *= m->N;
             INRCT_REQUIRE(m->n_grid < (1LL << 31), "grid too large for int32 indices");
             m->fov.build(m->dim, m->N);
+            {
+                int dev = 0, ncu = 0;
+                INRCT_CHECK_HIP(hipGetDevice(&dev));
+                INRCT_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+                m->n_cu = ncu > 0 ? ncu : 256;
+            }
             m->n_fov = m->fov.n;
             INRCT_REQUIRE(m->n_fov >= 1, "empty FOV");
             m->max_k = std::min<long long>(max_k, m->n_fov);
@@ -842,8 +1328,8 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             for (int l = l_first; l <= L; ++l) {
                 const int KS = ksteps(layer_K(a.kind, a.n_freq, d, W, l), kps);
                 m->frag_off[l] = (long long)fl.size();
-                for (int mt = 0; mt < MT; ++mt)
-                    for (int s = 0; s < KS; ++s) {
+                for (int s = 0; s < KS; ++s)
+                    for (int mt = 0; mt < MT; ++mt) {
                         fl.push_back(l);
                         fm.push_back(mt);
                         fs.push_back(s);
@@ -853,14 +1339,42 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             for (int l = 2; l <= L; ++l) {
                 const int NS = W / kps;
                 m->fragT_off[l] = (long long)fl.size() - m->nfrag;
-                for (int mt = 0; mt < MT; ++mt)
-                    for (int s = 0; s < NS; ++s) {
+                for (int s = 0; s < NS; ++s)
+                    for (int mt = 0; mt < MT; ++mt) {
                         fl.push_back(l);
                         fm.push_back(mt);
                         fs.push_back(s);
                     }
             }
             m->nfragT = (long long)fl.size() - m->nfrag;
+            if (bf && W == 256) {
+                // chunk stream of the width-256 LDS kernel: layer 1 by k-step
+                // (8 M-tiles), hidden layers by half, then k-step pairs x 4 M-tiles
+                std::vector<int> hl, hm, hs;
+                if (a.kind == INRCT_FFN) {
+                    const int KS1 = ksteps(layer_K(a.kind, a.n_freq, d, W, 1), 16);
+                    for (int s = 0; s < KS1; ++s)
+                        for (int mt = 0; mt < 8; ++mt) {
+                            hl.push_back(1);
+                            hm.push_back(mt);
+                            hs.push_back(s);
+                        }
+                }
+                for (int l = 2; l <= L; ++l)
+                    for (int half = 0; half < 2; ++half)
+                        for (int pr = 0; pr <= 8; ++pr)
+                            for (int j = 0; j < 2; ++j)
+                                for (int mt = 0; mt < 4; ++mt) {
+                                    hl.push_back(l);
+                                    hm.push_back(half * 4 + mt);
+                                    hs.push_back(2 * pr + j);
+                                }
+                m->nfrag_h = (long long)hl.size();
+                upload(m->pkh_layer, hl);
+                upload(m->pkh_mt, hm);
+                upload(m->pkh_s, hs);
+                m->frag_h.alloc(m->nfrag_h * 64 * 16);
+            }
             upload(m->pk_layer, fl);
             upload(m->pk_mt, fm);
             upload(m->pk_s, fs);

@@ -6,6 +6,7 @@
 struct inrct_model {
     inr_arch arch;
     int N = 0, dim = 0;
+    int n_cu = 256;  // compute units of the device the handle was created on
     long long n_grid = 0, n_params = 0, n_fov = 0, max_k = 0;
     inrct::FovHost fov;
 
@@ -18,6 +19,9 @@ struct inrct_model {
     long long nfrag = 0, nfragT = 0;
     long long frag_off[10] = {0}, fragT_off[10] = {0};
     inrct::DevBuf frag, fragT, pk_layer, pk_mt, pk_s;
+    // chunk stream of the width-256 BF16 grid-evaluation kernel
+    long long nfrag_h = 0;
+    inrct::DevBuf frag_h, pkh_layer, pkh_mt, pkh_s;
 
     // VJP chunk scratch
     long long P_alloc = 0;       // points per chunk (row stride)
