@@ -87,3 +87,35 @@ def sample_indices(fov_idx, k, seed, step):
     """The index set I as grid linear indices (ascending)."""
     fov_idx = np.asarray(fov_idx)
     return fov_idx[sample_ranks(fov_idx.size, k, seed, step)]
+
+
+def _mix64_np(z):
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def sample_ranks_np(n, k, seed, step):
+    """sample_ranks with the Feistel rounds vectorised over j (uint64
+    arithmetic wraps modulo 2^64 as the specification requires)."""
+    if not 0 < k <= n:
+        raise ValueError("need 0 < k <= n")
+    hb = half_bits(n)
+    keys = [np.uint64(kk) for kk in round_keys(seed, step)]
+    mask = np.uint64((1 << hb) - 1)
+    sh = np.uint64(hb)
+    top = np.uint64(64 - hb)
+
+    def E(x):
+        L, R = x >> sh, x & mask
+        for K in keys:
+            L, R = R, L ^ (_mix64_np(K ^ R) >> top)
+        return (L << sh) | R
+
+    with np.errstate(over="ignore"):
+        y = E(np.arange(k, dtype=np.uint64))
+        bad = y >= np.uint64(n)
+        while bad.any():
+            y[bad] = E(y[bad])
+            bad = y >= np.uint64(n)
+    return np.sort(y.astype(np.int64))

@@ -1,0 +1,343 @@
+// Circular cone-beam Joseph projector P and its exact voxel-driven
+// transpose (Sec. III: P in R^{m x n}; v = P^T r).
+//
+// For a flat detector whose row axis is the rotation axis, every ray of
+// detector column a has the same in-plane direction, and the z position of
+// ray (a, b) where it crosses slice s is affine in both s and b.  The host
+// reduces each (view, column) to six 24.40 fixed-point integers in float64
+// (see ConeCol); P and P^T evaluate the same integers, so P^T applies
+// exactly the interpolation weights P applies, and neither does float64
+// work per sample.
+//
+// P: one ray per lane, 64 columns x 4 rows per workgroup, slices visited in
+// order.  Rays whose principal axis is x read a transposed copy of the
+// volume ([z][x][y]) so that neighbouring lanes read neighbouring addresses
+// in both cases.
+// P^T: one thread per (x, y) voxel column segment of kZc voxels; for each
+// view, the detector columns whose stencil covers the voxel in-plane are
+// found once per segment, then a monotone sweep over detector rows gathers
+// the step-weighted residual for the kZc voxels.  No atomics.
+#include <math.h>
+
+#include "geom.h"
+
+namespace inrct {
+
+static const double kFix40 = 1099511627776.0;  // 2^40
+
+// ------------------------------------------------------------------ host
+void cone_build(inrct_geom *hd) {
+    const ct_geometry &g = hd->g;
+    const int N = hd->N;
+    const double h = 2.0 / N;
+    const double c0 = -1.0 + 0.5 * h;
+    const double tau = 1e-9;
+    const double cv = 0.5 * (double)(g.n_v - 1);
+    std::vector<ConeCol> cols((size_t)g.n_views * g.n_u);
+    std::vector<ConeView> views(g.n_views);
+    bool any_x = false;
+    for (int j = 0; j < g.n_views; ++j) {
+        const double cs = cos(g.angles[j]), sn = sin(g.angles[j]);
+        ConeView &vg = views[j];
+        vg.Sx = g.sid * cs;
+        vg.Sy = g.sid * sn;
+        vg.Cx = -g.idd * cs;
+        vg.Cy = -g.idd * sn;
+        vg.eux = -sn;
+        vg.euy = cs;
+        vg.any_x = vg.any_y = 0;
+        const double Sz = 0.0, dz0 = 0.0;
+        for (int a = 0; a < g.n_u; ++a) {
+            const double ua = ((double)a - 0.5 * (double)(g.n_u - 1)) * g.du;
+            const double dx = vg.Cx - vg.Sx + ua * vg.eux;
+            const double dy = vg.Cy - vg.Sy + ua * vg.euy;
+            ConeCol &c = cols[(size_t)j * g.n_u + a];
+            c.ypr = fabs(dy) >= (1.0 - tau) * fabs(dx) ? 1 : 0;
+            const double dax = c.ypr ? dy : dx, dot = c.ypr ? dx : dy;
+            const double pax = c.ypr ? vg.Sy : vg.Sx, pot = c.ypr ? vg.Sx : vg.Sy;
+            const double inv = 1.0 / dax;
+            const double t0 = (c0 - pax) * inv;
+            const double tN = t0 + (N - 1) * h * inv;
+            INRCT_REQUIRE(t0 > 0 && tN > 0, "a grid slice lies behind the source");
+            const double phio = (pot + t0 * dot + 1.0) / h - 0.5;
+            c.F0o = llrint(phio * kFix40);
+            c.dFo = llrint(dot * inv * kFix40);
+            const double Z0 = (Sz + t0 * dz0 + 1.0) / h - 0.5 - t0 * cv * g.dv / h;
+            c.Z0 = llrint(Z0 * kFix40);
+            c.D0 = llrint((inv * dz0 - inv * cv * g.dv) * kFix40);
+            c.Z1 = llrint(t0 * g.dv / h * kFix40);
+            c.D1 = llrint(inv * g.dv * kFix40);
+            c.dxy2 = (float)(dx * dx + dy * dy);
+            c.dz0 = (float)dz0;
+            c.hinv = (float)(h * fabs(inv));
+            if (c.ypr) vg.any_y = 1; else { vg.any_x = 1; any_x = true; }
+        }
+    }
+    upload(hd->ccols, cols);
+    upload(hd->cviews, views);
+    hd->any_x = any_x;
+    if (any_x) hd->ut.alloc(sizeof(float) * (size_t)N * N * N);
+}
+
+// ---------------------------------------------------------------- device
+__device__ __forceinline__ int fx40_int(long long F) { return (int)(F >> 40); }
+__device__ __forceinline__ float fx40_frac(long long F) {
+    return (float)(unsigned int)(F >> 8) * 2.3283064365386963e-10f;
+}
+
+// Step length h |d| / |d_axis| of ray (column record c, row b), float32,
+// written with explicitly rounded operations so P and P^T agree bitwise.
+__device__ __forceinline__ float cone_step(const ConeDev &g, const ConeCol &c, int b) {
+    const float vb = __fmul_rn(__fsub_rn((float)b, g.cvf), g.dvf);
+    const float dz = __fadd_rn(c.dz0, vb);
+    return __fmul_rn(c.hinv, __fsqrt_rn(__fadd_rn(c.dxy2, __fmul_rn(dz, dz))));
+}
+
+// Slices where floor(phi) in [-1, N - 1] (a superset; taps are bounds-checked).
+__device__ __forceinline__ void range40(long long F0, long long dF, int N, int *lo, int *hi) {
+    const double phi0 = (double)F0 * (1.0 / kFix40);
+    const double sl = (double)dF * (1.0 / kFix40);
+    double a, b;
+    if (sl > 0) {
+        a = (-1.0 - phi0) / sl;
+        b = ((double)N - phi0) / sl;
+    } else if (sl < 0) {
+        a = ((double)N - phi0) / sl;
+        b = (-1.0 - phi0) / sl;
+    } else if (phi0 >= -1.0 && phi0 < (double)N) {
+        a = 0;
+        b = N - 1;
+    } else {
+        a = 1;
+        b = 0;
+    }
+    double l = floor(a) - 1.0, r = ceil(b) + 1.0;
+    if (l < 0) l = 0;
+    if (r > N - 1) r = N - 1;
+    *lo = (int)l;
+    *hi = (int)r;
+}
+
+// ut[z][x][y] = u[z][y][x]
+__global__ __launch_bounds__(256) void k_transpose_xy(const float *__restrict__ u,
+                                                      float *__restrict__ ut, int N) {
+    __shared__ float tile[32][33];
+    const int z = blockIdx.z;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const size_t base = (size_t)z * N * N;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int y = y0 + k, x = x0 + tx;
+        if (x < N && y < N) tile[k][tx] = u[base + (size_t)y * N + x];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int x = x0 + k, y = y0 + tx;
+        if (x < N && y < N) ut[base + (size_t)x * N + y] = tile[tx][k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ u,
+                                                  const float *__restrict__ ut,
+                                                  float *__restrict__ z) {
+    const int a = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int b = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.z;
+    if (a >= g.Nu || b >= g.Nv) return;
+    const ConeCol c = g.col[(size_t)j * g.Nu + a];
+    const long long F0z = c.Z0 + (long long)b * c.Z1;
+    const long long dFz = c.D0 + (long long)b * c.D1;
+    const int N = g.N;
+    int lo1, hi1, lo2, hi2;
+    range40(c.F0o, c.dFo, N, &lo1, &hi1);
+    range40(F0z, dFz, N, &lo2, &hi2);
+    const int lo = max(lo1, lo2), hi = min(hi1, hi2);
+    const float *__restrict__ src = c.ypr ? u : ut;
+    const long long NN = (long long)N * N;
+    long long Fo = c.F0o + (long long)lo * c.dFo;
+    long long Fz = F0z + (long long)lo * dFz;
+    float acc = 0.f;
+    for (int s = lo; s <= hi; ++s, Fo += c.dFo, Fz += dFz) {
+        const int io = fx40_int(Fo), iz = fx40_int(Fz);
+        const float wo = fx40_frac(Fo), wz = fx40_frac(Fz);
+        const bool o0 = (unsigned)io < (unsigned)N, o1 = (unsigned)(io + 1) < (unsigned)N;
+        const bool z0 = (unsigned)iz < (unsigned)N, z1 = (unsigned)(iz + 1) < (unsigned)N;
+        const long long base = ((long long)iz * N + s) * N + io;
+        float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
+        if (z0 && o0) v00 = src[base];
+        if (z0 && o1) v01 = src[base + 1];
+        if (z1 && o0) v10 = src[base + NN];
+        if (z1 && o1) v11 = src[base + NN + 1];
+        acc += (1.f - wz) * ((1.f - wo) * v00 + wo * v01) + wz * ((1.f - wo) * v10 + wo * v11);
+    }
+    z[((size_t)j * g.Nv + b) * g.Nu + a] = acc * cone_step(g, c, b);
+}
+
+// rs = r * step length (applied on the ray side of P^T)
+__global__ __launch_bounds__(256) void k_cone_prescale(ConeDev g, const float *__restrict__ r,
+                                                       float *__restrict__ rs) {
+    const int a = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int b = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.z;
+    if (a >= g.Nu || b >= g.Nv) return;
+    const size_t i = ((size_t)j * g.Nv + b) * g.Nu + a;
+    rs[i] = r[i] * cone_step(g, g.col[(size_t)j * g.Nu + a], b);
+}
+
+// Columns whose ray crosses the in-plane segment p1-p2 (central projection
+// of the end points, rounded outwards).
+__device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, double p1x,
+                                          double p1y, double p2x, double p2y, int *lo, int *hi) {
+    const double ax = vg.Sx - vg.Cx, ay = vg.Sy - vg.Cy;
+    const double D1x = p1x - vg.Sx, D1y = p1y - vg.Sy;
+    const double D2x = p2x - vg.Sx, D2y = p2y - vg.Sy;
+    const double u1 = (ax * D1y - ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
+    const double u2 = (ax * D2y - ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
+    const double c = 0.5 * (double)(g.Nu - 1);
+    const double a1 = u1 / g.du + c, a2 = u2 / g.du + c;
+    double l = floor(fmin(a1, a2)), r = ceil(fmax(a1, a2));
+    if (l < 0) l = 0;
+    if (r > g.Nu - 1) r = g.Nu - 1;
+    *lo = (int)l;
+    *hi = (int)r;
+}
+
+// (P^T r) for voxels (ix, iy, z0 .. z0 + ZC - 1), accumulated into acc.
+// rs is the step-weighted residual.
+template <int ZC>
+__device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__restrict__ rs,
+                                            int ix, int iy, int z0, float (&acc)[ZC]) {
+    const double h = g.h;
+    const double x = -1.0 + (ix + 0.5) * h, y = -1.0 + (iy + 0.5) * h;
+    const int Nu = g.Nu, Nv = g.Nv;
+    for (int j = 0; j < g.V; ++j) {
+        const ConeView vg = g.view[j];
+        const float *rj = rs + (size_t)j * Nv * Nu;
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool ypass = pass == 0;
+            if (ypass ? !vg.any_y : !vg.any_x) continue;
+            const int s = ypass ? iy : ix, o = ypass ? ix : iy;
+            int lo, hi;
+            if (ypass) cone_cols(g, vg, x - h, y, x + h, y, &lo, &hi);
+            else cone_cols(g, vg, x, y - h, x, y + h, &lo, &hi);
+            for (int a = lo; a <= hi; ++a) {
+                const ConeCol c = g.col[(size_t)j * Nu + a];
+                if ((c.ypr != 0) != ypass) continue;
+                const long long Fo = c.F0o + (long long)s * c.dFo;
+                const int io = fx40_int(Fo);
+                if (io != o && io != o - 1) continue;
+                const float fo = fx40_frac(Fo);
+                const float wo = io == o ? 1.f - fo : fo;
+                const long long E0 = c.Z0 + (long long)s * c.D0;
+                const long long E1 = c.Z1 + (long long)s * c.D1;  // > 0
+                // first row whose stencil reaches z0 - 1
+                const long long lo_t = (long long)(z0 - 1) << 40;
+                double bd = floor((double)(lo_t - E0) / (double)E1) - 1.0;
+                bd = bd < 0.0 ? 0.0 : (bd > (double)Nv ? (double)Nv : bd);
+                int b = (int)bd;
+                long long ph = E0 + (long long)b * E1;
+                while (b > 0 && ph - E1 >= lo_t) {
+                    --b;
+                    ph -= E1;
+                }
+                while (b < Nv && ph < lo_t) {
+                    ++b;
+                    ph += E1;
+                }
+                const float *rc = rj + a;
+#pragma unroll
+                for (int jz = 0; jz < ZC; ++jz) {
+                    const int iz = z0 + jz;
+                    int bb = b;
+                    long long pp = ph;
+                    while (bb < Nv) {
+                        const int i0 = fx40_int(pp);
+                        if (i0 > iz) break;
+                        const float w = fx40_frac(pp);
+                        acc[jz] += wo * (i0 == iz ? 1.f - w : w) * rc[(size_t)bb * Nu];
+                        ++bb;
+                        pp += E1;
+                    }
+                    while (b < Nv && fx40_int(ph) < iz) {
+                        ++b;
+                        ph += E1;
+                    }
+                }
+            }
+        }
+    }
+}
+
+constexpr int kZc = 16;
+
+__global__ __launch_bounds__(256) void k_cone_bp(ConeDev g, const float *__restrict__ rs,
+                                                 float *__restrict__ v) {
+    const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int z0 = blockIdx.z * kZc;
+    if (ix >= g.N || iy >= g.N) return;
+    float acc[kZc];
+#pragma unroll
+    for (int i = 0; i < kZc; ++i) acc[i] = 0.f;
+    cone_gather<kZc>(g, rs, ix, iy, z0, acc);
+    const size_t NN = (size_t)g.N * g.N;
+#pragma unroll
+    for (int i = 0; i < kZc; ++i)
+        if (z0 + i < g.N) v[(size_t)(z0 + i) * NN + (size_t)iy * g.N + ix] = acc[i];
+}
+
+__global__ __launch_bounds__(256) void k_cone_bp_at(ConeDev g, const float *__restrict__ rs,
+                                                    const int32_t *__restrict__ idx, int64_t k,
+                                                    float *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= k) return;
+    const int64_t q = idx[t];
+    const int N = g.N;
+    float acc[1] = {0.f};
+    cone_gather<1>(g, rs, (int)(q % N), (int)((q / N) % N), (int)(q / ((int64_t)N * N)), acc);
+    out[t] = acc[0];
+}
+
+// ----------------------------------------------------------- host wrappers
+void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
+    const ConeDev d = hd->cone();
+    const float *ut = u;
+    if (hd->any_x) {
+        hipLaunchKernelGGL(k_transpose_xy, dim3((unsigned)cdiv(d.N, 32), (unsigned)cdiv(d.N, 32), d.N),
+                           dim3(256), 0, s, u, hd->ut.as<float>(), d.N);
+        INRCT_CHECK_LAUNCH();
+        ut = hd->ut.as<float>();
+    }
+    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)cdiv(d.Nu, 64), (unsigned)cdiv(d.Nv, 4), d.V),
+                       dim3(256), 0, s, d, u, ut, z);
+    INRCT_CHECK_LAUNCH();
+}
+
+static const float *cone_prescale(inrct_geom *hd, const float *r, hipStream_t s) {
+    const ConeDev d = hd->cone();
+    float *rs = hd->q.as<float>();
+    hipLaunchKernelGGL(k_cone_prescale, dim3((unsigned)cdiv(d.Nu, 64), (unsigned)cdiv(d.Nv, 4), d.V),
+                       dim3(256), 0, s, d, r, rs);
+    INRCT_CHECK_LAUNCH();
+    return rs;
+}
+
+void cone_backproject(inrct_geom *hd, const float *r, float *v, hipStream_t s) {
+    const float *rs = cone_prescale(hd, r, s);
+    const ConeDev d = hd->cone();
+    hipLaunchKernelGGL(k_cone_bp, dim3((unsigned)cdiv(d.N, 64), (unsigned)cdiv(d.N, 4),
+                                       (unsigned)cdiv(d.N, kZc)),
+                       dim3(256), 0, s, d, rs, v);
+    INRCT_CHECK_LAUNCH();
+}
+
+void cone_backproject_at(inrct_geom *hd, const float *r, const int32_t *idx, int64_t k,
+                         float *out, hipStream_t s) {
+    const float *rs = cone_prescale(hd, r, s);
+    const ConeDev d = hd->cone();
+    hipLaunchKernelGGL(k_cone_bp_at, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, d, rs, idx, k,
+                       out);
+    INRCT_CHECK_LAUNCH();
+}
+
+}  // namespace inrct

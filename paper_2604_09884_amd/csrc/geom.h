@@ -1,0 +1,108 @@
+// Internal geometry handle shared by the projector sources.
+#pragma once
+
+#include "common.h"
+
+namespace inrct {
+
+// 2D parallel beam: one record per (view, bin), 32.32 fixed point.
+struct ColGeom {
+    double t0;     // ray parameter at slice 0
+    double inv;    // 1 / d_axis
+    double p0z;    // unused in 2D
+    double dz0;    // unused in 2D
+    double dxy2;   // squared length of the ray direction
+    long long F0o; // 32.32 fixed-point phi_other at slice 0
+    long long dFo; // per-slice increment of phi_other
+    int ypr;       // 1: y is the principal axis
+    int pad;
+};
+
+struct ViewGeom {
+    double Sx, Sy, Cx, Cy, eux, euy, cs, sn;
+    int any_y, any_x;
+};
+
+struct GeomDev {
+    int kind, N, V, Nu, Nv;
+    double h, du, dv;
+    const ColGeom *col;   // [V][Nu]
+    const ViewGeom *view; // [V]
+};
+
+// 3D cone beam: one record per (view, detector column), 24.40 fixed point.
+// The interpolation positions of ray (column a, row b) at slice s are
+//   phi_other(s)  = F0o + s dFo
+//   phi_z(s, b)   = Z0 + s D0 + b (Z1 + s D1)
+// (exact integer arithmetic; the z position is affine in the detector row
+// because the row axis is the z axis).
+struct ConeCol {
+    long long F0o, dFo, Z0, D0, Z1, D1;
+    float dxy2;   // squared in-plane length of the ray direction
+    float dz0;    // z component of the direction before the row offset
+    float hinv;   // h / |d_axis|
+    int ypr;      // 1: y is the principal axis
+};
+
+struct ConeView {
+    double Sx, Sy, Cx, Cy, eux, euy;
+    int any_y, any_x;
+};
+
+struct ConeDev {
+    int N, V, Nu, Nv;
+    double h, du;
+    float dvf, cvf;        // row pitch and (Nv - 1)/2
+    const ConeCol *col;    // [V][Nu]
+    const ConeView *view;  // [V]
+};
+
+}  // namespace inrct
+
+struct inrct_geom {
+    ct_geometry g;
+    int N = 0, dim = 0;
+    std::vector<double> angles;
+    inrct::DevBuf cols, views, q, partials;
+    int n_partials = 0;
+    // cone beam
+    inrct::DevBuf ccols, cviews, ut;
+    bool any_x = false;
+    inrct::GeomDev dev() const {
+        inrct::GeomDev d;
+        d.kind = g.kind;
+        d.N = N;
+        d.V = g.n_views;
+        d.Nu = g.n_u;
+        d.Nv = g.n_v;
+        d.h = 2.0 / N;
+        d.du = g.du;
+        d.dv = g.dv;
+        d.col = cols.as<inrct::ColGeom>();
+        d.view = views.as<inrct::ViewGeom>();
+        return d;
+    }
+    inrct::ConeDev cone() const {
+        inrct::ConeDev d;
+        d.N = N;
+        d.V = g.n_views;
+        d.Nu = g.n_u;
+        d.Nv = g.n_v;
+        d.h = 2.0 / N;
+        d.du = g.du;
+        d.dvf = (float)g.dv;
+        d.cvf = 0.5f * (float)(g.n_v - 1);
+        d.col = ccols.as<inrct::ConeCol>();
+        d.view = cviews.as<inrct::ConeView>();
+        return d;
+    }
+    int64_t m() const { return (int64_t)g.n_views * g.n_v * g.n_u; }
+};
+
+namespace inrct {
+void cone_build(inrct_geom *h);
+void cone_project(inrct_geom *h, const float *u, float *z, hipStream_t s);
+void cone_backproject(inrct_geom *h, const float *r, float *v, hipStream_t s);
+void cone_backproject_at(inrct_geom *h, const float *r, const int32_t *idx, int64_t k,
+                         float *out, hipStream_t s);
+}  // namespace inrct

@@ -1,7 +1,7 @@
 // Internal definition of the model handle (shared by mlp.hip and step.hip).
 #pragma once
 
-#include "common.h"
+#include "geom.h"
 
 struct inrct_model {
     inr_arch arch;

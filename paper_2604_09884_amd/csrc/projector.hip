@@ -1,43 +1,18 @@
-// Joseph ray-driven projector P, its voxel-driven exact transpose P^T and
-// the data-fidelity residuals (Sec. II, Sec. III of the paper).
+// 2D parallel-beam Joseph projector P, its voxel-driven exact transpose P^T,
+// the data-fidelity residuals (Sec. II, Sec. III of the paper) and the
+// geometry handle.  The cone-beam kernels are in cone.hip.
 //
 // Geometry is reduced on the host, in float64, to one record per (view,
-// detector column): the principal axis, 1/d_axis, the ray parameter at the
+// detector bin): the principal axis, 1/d_axis, the ray parameter at the
 // first slice and the interpolation position of the in-plane "other"
 // coordinate as a 32.32 fixed-point start value and per-slice increment.
-// Per-ray z parameters (cone beam) are derived on the device by one float64
-// function shared by P and P^T.  Because the interpolation position at slice
-// s is the exact integer F0 + s * dF in both kernels, P^T applies exactly
-// the weights P applies.
+// Because the interpolation position at slice s is the exact integer
+// F0 + s * dF in both kernels, P^T applies exactly the weights P applies.
 #include <math.h>
 
-#include "common.h"
+#include "geom.h"
 
 namespace inrct {
-
-struct ColGeom {
-    double t0;     // ray parameter at slice 0
-    double inv;    // 1 / d_axis
-    double p0z;    // ray origin z (cone)
-    double dz0;    // ray direction z before the detector-row offset (cone)
-    double dxy2;   // squared in-plane length of the ray direction
-    long long F0o; // 32.32 fixed-point phi_other at slice 0
-    long long dFo; // per-slice increment of phi_other
-    int ypr;       // 1: y is the principal axis
-    int pad;
-};
-
-struct ViewGeom {
-    double Sx, Sy, Cx, Cy, eux, euy, cs, sn;
-    int any_y, any_x;
-};
-
-struct GeomDev {
-    int kind, N, V, Nu, Nv;
-    double h, du, dv;
-    const ColGeom *col;   // [V][Nu]
-    const ViewGeom *view; // [V]
-};
 
 static const double kFix = 4294967296.0;       // 2^32
 static const float kInvFix = 2.3283064365386963e-10f;  // 2^-32
@@ -108,19 +83,6 @@ static void build_tables(const ct_geometry &g, int N, std::vector<ColGeom> &cols
 }
 
 // --------------------------------------------------------- device helpers
-// Per-ray z parameters of a cone-beam ray (column record c, detector row b).
-__device__ __forceinline__ void ray_z(const GeomDev &g, const ColGeom &c, int b,
-                                      long long *F0z, long long *dFz,
-                                      float *step) {
-#pragma clang fp contract(off)
-    const double vb = ((double)b - 0.5 * (double)(g.Nv - 1)) * g.dv;
-    const double dz = c.dz0 + vb;
-    const double phi0 = (c.p0z + c.t0 * dz + 1.0) / g.h - 0.5;
-    *F0z = __double2ll_rn(phi0 * kFix);
-    *dFz = __double2ll_rn((dz * c.inv) * kFix);
-    *step = (float)(g.h * sqrt(c.dxy2 + dz * dz) * fabs(c.inv));
-}
-
 __device__ __forceinline__ float ray_step2d(const GeomDev &g, const ColGeom &c) {
 #pragma clang fp contract(off)
     return (float)(g.h * sqrt(c.dxy2) * fabs(c.inv));
@@ -180,67 +142,7 @@ __global__ __launch_bounds__(256) void k_proj2d(GeomDev g, const float *__restri
     z[(size_t)j * g.Nu + k] = acc * ray_step2d(g, c);
 }
 
-// ----------------------------------------------------------- forward, 3D
-__global__ __launch_bounds__(256) void k_proj3d(GeomDev g, const float *__restrict__ u,
-                                                float *__restrict__ z) {
-    const int a = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int b = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int j = blockIdx.z;
-    if (a >= g.Nu || b >= g.Nv) return;
-    const ColGeom c = g.col[(size_t)j * g.Nu + a];
-    long long F0z, dFz;
-    float step;
-    ray_z(g, c, b, &F0z, &dFz, &step);
-    const int N = g.N;
-    int lo1, hi1, lo2, hi2;
-    slice_range(c.F0o, c.dFo, N, &lo1, &hi1);
-    slice_range(F0z, dFz, N, &lo2, &hi2);
-    const int lo = max(lo1, lo2), hi = min(hi1, hi2);
-    long long Fo = c.F0o + (long long)lo * c.dFo;
-    long long Fz = F0z + (long long)lo * dFz;
-    const size_t NN = (size_t)N * N;
-    // y-principal: voxel (o, s, iz) -> iz*NN + s*N + o ; x-principal: iz*NN + o*N + s
-    const size_t so = c.ypr ? 1 : (size_t)N;
-    const size_t ss = c.ypr ? (size_t)N : 1;
-    float acc = 0.f;
-    for (int s = lo; s <= hi; ++s, Fo += c.dFo, Fz += dFz) {
-        const int io = fx_int(Fo), iz = fx_int(Fz);
-        const float wo = fx_frac(Fo), wz = fx_frac(Fz);
-        const bool o0 = (unsigned)io < (unsigned)N, o1 = (unsigned)(io + 1) < (unsigned)N;
-        const bool z0 = (unsigned)iz < (unsigned)N, z1 = (unsigned)(iz + 1) < (unsigned)N;
-        const size_t base = (size_t)s * ss + (size_t)io * so + (size_t)iz * NN;
-        float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;  // [z][o]
-        if (z0 && o0) v00 = u[base];
-        if (z0 && o1) v01 = u[base + so];
-        if (z1 && o0) v10 = u[base + NN];
-        if (z1 && o1) v11 = u[base + NN + so];
-        acc += (1.f - wz) * ((1.f - wo) * v00 + wo * v01) +
-               wz * ((1.f - wo) * v10 + wo * v11);
-    }
-    z[((size_t)j * g.Nv + b) * g.Nu + a] = acc * step;
-}
-
 // ------------------------------------------------ adjoint (gather) helpers
-// Detector columns whose ray crosses the in-plane segment between p1 and p2
-// (on one slice): a real interval from the central projection of the two
-// end points, rounded outwards.  Cone beam.
-__device__ __forceinline__ void cone_col_range(const GeomDev &g, const ViewGeom &vg,
-                                               double p1x, double p1y, double p2x,
-                                               double p2y, int *lo, int *hi) {
-    const double ax = vg.Sx - vg.Cx, ay = vg.Sy - vg.Cy;
-    double D1x = p1x - vg.Sx, D1y = p1y - vg.Sy;
-    double D2x = p2x - vg.Sx, D2y = p2y - vg.Sy;
-    const double u1 = (ax * D1y - ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
-    const double u2 = (ax * D2y - ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
-    const double c = 0.5 * (double)(g.Nu - 1);
-    const double a1 = u1 / g.du + c, a2 = u2 / g.du + c;
-    double l = floor(fmin(a1, a2)), r = ceil(fmax(a1, a2));
-    if (l < 0) l = 0;
-    if (r > g.Nu - 1) r = g.Nu - 1;
-    *lo = (int)l;
-    *hi = (int)r;
-}
-
 __device__ __forceinline__ void par_col_range(const GeomDev &g, const ViewGeom &vg,
                                               double p1x, double p1y, double p2x,
                                               double p2y, int *lo, int *hi) {
@@ -293,66 +195,12 @@ __device__ float bp_pixel_2d(const GeomDev &g, const float *__restrict__ r, int 
     return acc;
 }
 
-// (P^T r) at voxel (ix, iy, iz) of a cone-beam geometry.
-__device__ float bp_voxel_3d(const GeomDev &g, const float *__restrict__ r, int ix,
-                             int iy, int iz) {
-    const double h = g.h;
-    const double x = -1.0 + (ix + 0.5) * h, y = -1.0 + (iy + 0.5) * h;
-    const double cz = 0.5 * (double)(g.Nv - 1);
-    float acc = 0.f;
-    for (int j = 0; j < g.V; ++j) {
-        const ViewGeom vg = g.view[j];
-        const float *rj = r + (size_t)j * g.Nv * g.Nu;
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool ypass = pass == 0;
-            if (ypass ? !vg.any_y : !vg.any_x) continue;
-            const int s = ypass ? iy : ix, o = ypass ? ix : iy;
-            int lo, hi;
-            if (ypass) cone_col_range(g, vg, x - h, y, x + h, y, &lo, &hi);
-            else cone_col_range(g, vg, x, y - h, x, y + h, &lo, &hi);
-            for (int a = lo; a <= hi; ++a) {
-                const ColGeom c = g.col[(size_t)j * g.Nu + a];
-                if ((c.ypr != 0) != ypass) continue;
-                bool hit;
-                const float wo = stencil_weight(c.F0o + (long long)s * c.dFo, o, &hit);
-                if (!hit) continue;
-                // rows whose z-position at this slice falls in [iz-1, iz+1)
-                const double ts = c.t0 + (double)s * h * c.inv;
-                const double va = ((iz - 0.5) * h - 1.0 - c.p0z) / ts - c.dz0;
-                const double vb = ((iz + 1.5) * h - 1.0 - c.p0z) / ts - c.dz0;
-                double bl = floor(fmin(va, vb) / g.dv + cz);
-                double br = ceil(fmax(va, vb) / g.dv + cz);
-                if (bl < 0) bl = 0;
-                if (br > g.Nv - 1) br = g.Nv - 1;
-                for (int b = (int)bl; b <= (int)br; ++b) {
-                    long long F0z, dFz;
-                    float step;
-                    ray_z(g, c, b, &F0z, &dFz, &step);
-                    bool hz;
-                    const float wz = stencil_weight(F0z + (long long)s * dFz, iz, &hz);
-                    if (hz) acc += wo * wz * step * rj[(size_t)b * g.Nu + a];
-                }
-            }
-        }
-    }
-    return acc;
-}
-
 __global__ __launch_bounds__(256) void k_bproj2d(GeomDev g, const float *__restrict__ r,
                                                  float *__restrict__ v) {
     const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
     const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (ix >= g.N || iy >= g.N) return;
     v[(size_t)iy * g.N + ix] = bp_pixel_2d(g, r, ix, iy);
-}
-
-__global__ __launch_bounds__(256) void k_bproj3d(GeomDev g, const float *__restrict__ r,
-                                                 float *__restrict__ v) {
-    const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int iz = blockIdx.z;
-    if (ix >= g.N || iy >= g.N) return;
-    v[((size_t)iz * g.N + iy) * g.N + ix] = bp_voxel_3d(g, r, ix, iy, iz);
 }
 
 __global__ __launch_bounds__(256) void k_bproj_at(GeomDev g, const float *__restrict__ r,
@@ -362,9 +210,7 @@ __global__ __launch_bounds__(256) void k_bproj_at(GeomDev g, const float *__rest
     if (t >= k) return;
     const int64_t q = idx[t];
     const int N = g.N;
-    const int ix = (int)(q % N), iy = (int)((q / N) % N);
-    if (g.kind == INRCT_PAR2D) out[t] = bp_pixel_2d(g, r, ix, iy);
-    else out[t] = bp_voxel_3d(g, r, ix, iy, (int)(q / ((int64_t)N * N)));
+    out[t] = bp_pixel_2d(g, r, (int)(q % N), (int)((q / N) % N));
 }
 
 // ---------------------------------------------------------------- residual
@@ -426,29 +272,6 @@ __global__ __launch_bounds__(256) void k_ramp(const float *__restrict__ q, float
 // ==================================================================== ABI
 using namespace inrct;
 
-struct inrct_geom {
-    ct_geometry g;
-    int N = 0, dim = 0;
-    std::vector<double> angles;
-    DevBuf cols, views, q, partials;
-    int n_partials = 0;
-    GeomDev dev() const {
-        GeomDev d;
-        d.kind = g.kind;
-        d.N = N;
-        d.V = g.n_views;
-        d.Nu = g.n_u;
-        d.Nv = g.n_v;
-        d.h = 2.0 / N;
-        d.du = g.du;
-        d.dv = g.dv;
-        d.col = cols.as<ColGeom>();
-        d.view = views.as<ViewGeom>();
-        return d;
-    }
-    int64_t m() const { return (int64_t)g.n_views * g.n_v * g.n_u; }
-};
-
 namespace inrct {
 int64_t geom_rays(const inrct_geom *g) { return g->m(); }
 int geom_dim(const inrct_geom *g) { return g->dim; }
@@ -459,12 +282,10 @@ void project(inrct_geom *geom, const float *u, float *z, hipStream_t s) {
     if (d.kind == INRCT_PAR2D) {
         hipLaunchKernelGGL(k_proj2d, dim3((unsigned)cdiv(d.Nu, 256), d.V), dim3(256),
                            0, s, d, u, z);
+        INRCT_CHECK_LAUNCH();
     } else {
-        hipLaunchKernelGGL(k_proj3d,
-                           dim3((unsigned)cdiv(d.Nu, 64), (unsigned)cdiv(d.Nv, 4), d.V),
-                           dim3(256), 0, s, d, u, z);
+        cone_project(geom, u, z, s);
     }
-    INRCT_CHECK_LAUNCH();
 }
 
 void backproject(inrct_geom *geom, const float *r, float *v, hipStream_t s) {
@@ -472,17 +293,19 @@ void backproject(inrct_geom *geom, const float *r, float *v, hipStream_t s) {
     if (d.kind == INRCT_PAR2D) {
         hipLaunchKernelGGL(k_bproj2d, dim3((unsigned)cdiv(d.N, 64), (unsigned)cdiv(d.N, 4)),
                            dim3(256), 0, s, d, r, v);
+        INRCT_CHECK_LAUNCH();
     } else {
-        hipLaunchKernelGGL(k_bproj3d,
-                           dim3((unsigned)cdiv(d.N, 64), (unsigned)cdiv(d.N, 4), d.N),
-                           dim3(256), 0, s, d, r, v);
+        cone_backproject(geom, r, v, s);
     }
-    INRCT_CHECK_LAUNCH();
 }
 
 void backproject_at(inrct_geom *geom, const float *r, const int32_t *idx, int64_t k,
                     float *out, hipStream_t s) {
     if (k <= 0) return;
+    if (geom->g.kind == INRCT_CONE3D) {
+        cone_backproject_at(geom, r, idx, k, out, s);
+        return;
+    }
     const GeomDev d = geom->dev();
     hipLaunchKernelGGL(k_bproj_at, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, d, r,
                        idx, k, out);
@@ -543,11 +366,15 @@ int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, inrct_geom **o
             h->dim = grid->dim;
             h->angles.assign(g->angles, g->angles + g->n_views);
             h->g.angles = h->angles.data();
-            std::vector<ColGeom> cols;
-            std::vector<ViewGeom> views;
-            build_tables(h->g, h->N, cols, views);
-            upload(h->cols, cols);
-            upload(h->views, views);
+            if (g->kind == INRCT_PAR2D) {
+                std::vector<ColGeom> cols;
+                std::vector<ViewGeom> views;
+                build_tables(h->g, h->N, cols, views);
+                upload(h->cols, cols);
+                upload(h->views, views);
+            } else {
+                cone_build(h);
+            }
             const int64_t m = h->m();
             h->n_partials = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(m, 4096)));
             h->partials.alloc(sizeof(double) * h->n_partials);

@@ -83,3 +83,9 @@ def test_inclusion_frequency_uniform():
     assert chi2 < 72.1
     # pairwise: P(i, j both in I) = k(k-1)/(n(n-1)) on average
     assert abs(cnt.sum() - draws * k) == 0
+
+
+def test_vectorised_sampler_equals_scalar_spec():
+    for n, k in [(1, 1), (7, 7), (5000, 300), (70001, 1000)]:
+        assert np.array_equal(sampler.sample_ranks_np(n, k, 31, 2),
+                              sampler.sample_ranks(n, k, 31, 2))
