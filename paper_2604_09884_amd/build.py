@@ -23,7 +23,7 @@ ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-         "-Wno-unused-result"]
+         "-Wno-unused-result", "-mllvm", "-pragma-unroll-threshold=1000000"]
 
 
 def sources():

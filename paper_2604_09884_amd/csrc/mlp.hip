@@ -172,7 +172,27 @@ struct ActSink {
     long long P;                    // points per chunk (row stride)
     long long act_off[kMaxDepth + 2];
     long long sig_off[kMaxDepth + 2];
+    uint4 *mask;                    // ReLU masks: [layer-1][P/32 tiles][64 lanes]
 };
+
+// 128 bits of "z > 0" for accumulator slots i = 16 mt + r (lane's point).
+template <int MT>
+__device__ __forceinline__ uint4 relu_bits(const f32x16 (&acc)[MT]) {
+    unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 16 * mt + r;
+            w[i >> 5] |= (acc[mt][r] > 0.f ? 1u : 0u) << (i & 31);
+        }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ float mask_bit(const uint4 &b, int i) {
+    const unsigned w = i < 32 ? b.x : (i < 64 ? b.y : (i < 96 ? b.z : b.w));
+    return (w >> (i & 31)) & 1u ? 1.f : 0.f;
+}
 
 template <int W, int NT, bool BF, int ACT, bool STORE>
 __device__ __forceinline__ void mlp_forward(const MlpDev &m, const float (&xc)[NT][3],
@@ -301,20 +321,35 @@ __device__ __forceinline__ void mlp_forward(const MlpDev &m, const float (&xc)[N
                 }
             }
             if constexpr (STORE) {
-                // a_{l-1} and (SIREN) its derivative factor, natural row order
+                // a_{l-1} (natural row order) for the weight gradients, and
+                // its ReLU mask bits (SIREN: the derivative factors)
                 if (pcol[nt] >= 0) {
+                    // 32-bit element offsets: a per-lane part kept opaque so the
+                    // per-row parts stay scalar (row constant x uniform stride)
+                    const int P = (int)sink.P;
+                    int base = (int)sink.act_off[l - 1] + pcol[nt] + 4 * h * P;
+                    asm volatile("" : "+v"(base));
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            const int row = 32 * mt + crow(r, h);
                             const float z = acc[nt][mt][r];
-                            sink.act[sink.act_off[l - 1] + (long long)row * sink.P + pcol[nt]] =
+                            sink.act[base + (32 * mt + 8 * (r / 4) + (r % 4)) * P] =
                                 (typename PR::Store)act_fn<ACT>(z, m.omega0);
-                            if constexpr (ACT == INRCT_SIREN)
-                                sink.sig[sink.sig_off[l - 1] + (long long)row * sink.P + pcol[nt]] =
-                                    act_grad<ACT>(z, m.omega0);
                         }
+                    if constexpr (ACT == INRCT_SIREN) {
+                        int sb = (int)sink.sig_off[l - 1] + pcol[nt] + 4 * h * P;
+                        asm volatile("" : "+v"(sb));
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int r = 0; r < 16; ++r)
+                                sink.sig[sb + (32 * mt + 8 * (r / 4) + (r % 4)) * P] =
+                                    act_grad<ACT>(acc[nt][mt][r], m.omega0);
+                    } else {
+                        sink.mask[((long long)(l - 2) * (sink.P / 32) + pcol[nt] / 32) * 64 + lane] =
+                            relu_bits<MT>(acc[nt]);
+                    }
                 }
             }
         }
@@ -919,21 +954,26 @@ __global__ __launch_bounds__(256) void k_vjp_tile(MlpDev m, const int32_t *__res
     const int L = m.L;
     const long long P = sink.P;
     // dlt rows: layer l (1..L) at dlt + (l-1)*W*P, output layer at dlt_off_L1
-    // ---- output layer: delta_{L+1} = cot; store a_L (+ SIREN factor)
+    // ---- output layer: delta_{L+1} = cot; store a_L; delta_L in registers
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         if (h == 0) dlt[dlt_off_L1 + pcol[nt]] = (St)cot[nt];
+        const int Pi = (int)P;
+        int ab = (int)sink.act_off[L] + pcol[nt] + 4 * h * Pi;
+        int db = (L - 1) * W * Pi + pcol[nt] + 4 * h * Pi;
+        asm volatile("" : "+v"(ab), "+v"(db));
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 32 * mt + crow(r, h);
+                const int ro = (32 * mt + 8 * (r / 4) + (r % 4)) * Pi;
                 const float z = acc[nt][mt][r];
-                sink.act[sink.act_off[L] + (long long)row * P + pcol[nt]] = (St)act_fn<ACT>(z, m.omega0);
+                sink.act[ab + ro] = (St)act_fn<ACT>(z, m.omega0);
                 // delta_L = cot * w_out * act'(z_L)
                 const float dl = cot[nt] * m.w_out[row] * act_grad<ACT>(z, m.omega0);
                 acc[nt][mt][r] = dl;
-                dlt[(long long)(L - 1) * W * P + (long long)row * P + pcol[nt]] = (St)dl;
+                dlt[db + ro] = (St)dl;
             }
     }
     const Op *fragT = (const Op *)m.fragT;
@@ -965,20 +1005,27 @@ __global__ __launch_bounds__(256) void k_vjp_tile(MlpDev m, const int32_t *__res
             }
         // delta_{l-1} = (W_l^T delta_l) * act'(z_{l-1})
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
+        for (int nt = 0; nt < NT; ++nt) {
+            uint4 bits = make_uint4(0, 0, 0, 0);
+            if constexpr (ACT == INRCT_FFN)
+                bits = sink.mask[((long long)(l - 2) * (P / 32) + pcol[nt] / 32) * 64 + lane];
+            const int Pi = (int)P;
+            int db = (l - 2) * W * Pi + pcol[nt] + 4 * h * Pi;
+            int sb = (int)sink.sig_off[l - 1] + pcol[nt] + 4 * h * Pi;
+            asm volatile("" : "+v"(db), "+v"(sb));
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int row = 32 * mt + crow(r, h);
-                    const long long e = (long long)row * P + pcol[nt];
+                    const int ro = (32 * mt + 8 * (r / 4) + (r % 4)) * Pi;
                     float g;
-                    if constexpr (ACT == INRCT_FFN) g = (float)sink.act[sink.act_off[l - 1] + e] > 0.f ? 1.f : 0.f;
-                    else g = sink.sig[sink.sig_off[l - 1] + e];
+                    if constexpr (ACT == INRCT_FFN) g = mask_bit(bits, 16 * mt + r);
+                    else g = sink.sig[sb + ro];
                     const float dl = acc[nt][mt][r] * g;
                     acc[nt][mt][r] = dl;
-                    dlt[(long long)(l - 2) * W * P + e] = (St)dl;
+                    dlt[db + ro] = (St)dl;
                 }
+        }
     }
 }
 
@@ -1231,6 +1278,7 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
     sink.act = m->act.as<St>();
     sink.sig = m->sig.as<float>();
     sink.P = m->P_alloc;
+    sink.mask = m->mask.as<uint4>();
     for (int l = 0; l < 10 && l < kMaxDepth + 2; ++l) {
         sink.act_off[l] = m->act_off[l];
         sink.sig_off[l] = m->sig_off[l];
@@ -1393,6 +1441,7 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             m->dlt_elems = (long long)L * W * P + P;
             const size_t es = bf ? 2 : 4;
             m->act.alloc(m->act_elems * es);
+            m->mask.alloc(sizeof(uint4) * (size_t)std::max(1, L - 1) * (P / 32) * 64);
             m->dlt.alloc(m->dlt_elems * es);
             if (a.kind == INRCT_SIREN) {
                 for (int l = 1; l <= L; ++l) m->sig_off[l] = (long long)(l - 1) * W * P;

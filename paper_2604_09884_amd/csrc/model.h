@@ -28,7 +28,7 @@ struct inrct_model {
     int kslice = 2048, nks = 0;  // split-K slice length and count
     long long act_off[10] = {0}, sig_off[10] = {0};
     long long act_elems = 0, dlt_elems = 0, sig_elems = 0;
-    inrct::DevBuf act, dlt, sig, part, tiles;
+    inrct::DevBuf act, dlt, sig, part, tiles, mask;
     int ntiles = 0;
 
     // sampler: FOV-rank membership bytes and per-block counts
