@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--mlp-dtype", default=None, choices=[None, "bf16", "fp32"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy before the steps (a "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -158,6 +161,12 @@ def main():
     log("n_fov %d, k %d, params %d, device memory in use %.2f GB"
         % (model.n_fov, k, model.n_params, (free0 - free1) / 1e9))
 
+    if a.calib_copy:
+        src = torch.ones(1 << 28, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for t in range(a.warmup):
         st.step(t)
     torch.cuda.synchronize()
