@@ -24,6 +24,7 @@
 namespace inrct {
 
 static const double kFix40 = 1099511627776.0;  // 2^40
+static const int kPad = 2;  // zero border of the padded volume copies
 
 // ------------------------------------------------------------------ host
 void cone_build(inrct_geom *hd) {
@@ -76,10 +77,26 @@ void cone_build(inrct_geom *hd) {
     upload(hd->ccols, cols);
     upload(hd->cviews, views);
     hd->any_x = any_x;
-    if (any_x) hd->ut.alloc(sizeof(float) * (size_t)N * N * N);
+    // zero-bordered copies of u in both layouts ([z][y][x] and [z][x][y]);
+    // the border is cleared once here and never written afterwards
+    const size_t Np = (size_t)N + 2 * kPad;
+    hd->ut.alloc(sizeof(float) * Np * Np * Np * (any_x ? 2 : 1));
+    INRCT_CHECK_HIP(hipMemset(hd->ut.ptr, 0, hd->ut.bytes));
+    INRCT_CHECK_HIP(hipDeviceSynchronize());
 }
 
 // ---------------------------------------------------------------- device
+// Workgroup id -> logical block: the hardware hands workgroups to the eight
+// XCDs round-robin; each XCD is given a contiguous range of logical blocks
+// so that blocks sharing volume or detector data run on the same L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+    const int xcd = bid & 7, pos = bid >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    const int cnt = per + (xcd < rem ? 1 : 0);
+    if (pos >= cnt) return -1;
+    return xcd * per + (xcd < rem ? xcd : rem) + pos;
+}
+
 __device__ __forceinline__ int fx40_int(long long F) { return (int)(F >> 40); }
 __device__ __forceinline__ float fx40_frac(long long F) {
     return (float)(unsigned int)(F >> 8) * 2.3283064365386963e-10f;
@@ -118,56 +135,84 @@ __device__ __forceinline__ void range40(long long F0, long long dF, int N, int *
     *hi = (int)r;
 }
 
-// ut[z][x][y] = u[z][y][x]
-__global__ __launch_bounds__(256) void k_transpose_xy(const float *__restrict__ u,
-                                                      float *__restrict__ ut, int N) {
+// The slice range [lo, hi] of range40 shrunk, with the exact fixed-point
+// positions, to slices whose stencil index floor(phi) lies in [-1, N - 1]
+// (phi is linear in s, so the valid slices form one interval).  Every tap
+// of every visited slice then lies in [-1, N].
+__device__ __forceinline__ void range40_exact(long long F0, long long dF, int N, int *lo,
+                                              int *hi) {
+    int l, r;
+    range40(F0, dF, N, &l, &r);
+    auto bad = [&](int s) {
+        const int i = fx40_int(F0 + (long long)s * dF);
+        return i < -1 || i > N - 1;
+    };
+    while (l <= r && bad(l)) ++l;
+    while (r >= l && bad(r)) --r;
+    *lo = l;
+    *hi = r;
+}
+
+// up[z+kPad][y+kPad][x+kPad] = u[z][y][x] and (if ut) ut[z+kPad][x+kPad][y+kPad] = u[z][y][x]
+__global__ __launch_bounds__(256) void k_pad_copy(const float *__restrict__ u,
+                                                  float *__restrict__ up,
+                                                  float *__restrict__ ut, int N) {
     __shared__ float tile[32][33];
+    const int Np = N + 2 * kPad;
     const int z = blockIdx.z;
     const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
     const size_t base = (size_t)z * N * N;
+    const size_t pbase = (size_t)(z + kPad) * Np * Np;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int k = ty; k < 32; k += 8) {
         const int y = y0 + k, x = x0 + tx;
-        if (x < N && y < N) tile[k][tx] = u[base + (size_t)y * N + x];
+        if (x < N && y < N) {
+            const float val = u[base + (size_t)y * N + x];
+            tile[k][tx] = val;
+            up[pbase + (size_t)(y + kPad) * Np + x + kPad] = val;
+        }
     }
+    if (ut == nullptr) return;
     __syncthreads();
     for (int k = ty; k < 32; k += 8) {
         const int x = x0 + k, y = y0 + tx;
-        if (x < N && y < N) ut[base + (size_t)x * N + y] = tile[tx][k];
+        if (x < N && y < N) ut[pbase + (size_t)(x + kPad) * Np + y + kPad] = tile[tx][k];
     }
 }
 
-__global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ u,
-                                                  const float *__restrict__ ut,
-                                                  float *__restrict__ z) {
-    const int a = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int b = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int j = blockIdx.z;
+// One ray per lane.  Reads the zero-bordered copies: over the exact slice
+// range every tap index lies in [-1, N], inside the kPad-wide zero border,
+// so no tap needs a bounds test.
+__global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ up,
+                                                  const float *__restrict__ utp,
+                                                  float *__restrict__ z, int ncx, int ncy) {
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb < 0) return;
+    const int a = (lb % ncx) * 64 + (threadIdx.x & 63);
+    const int b = ((lb / ncx) % ncy) * 4 + (threadIdx.x >> 6);
+    const int j = lb / (ncx * ncy);
     if (a >= g.Nu || b >= g.Nv) return;
     const ConeCol c = g.col[(size_t)j * g.Nu + a];
     const long long F0z = c.Z0 + (long long)b * c.Z1;
     const long long dFz = c.D0 + (long long)b * c.D1;
     const int N = g.N;
+    const int Np = N + 2 * kPad, Np2 = Np * Np;
     int lo1, hi1, lo2, hi2;
-    range40(c.F0o, c.dFo, N, &lo1, &hi1);
-    range40(F0z, dFz, N, &lo2, &hi2);
+    range40_exact(c.F0o, c.dFo, N, &lo1, &hi1);
+    range40_exact(F0z, dFz, N, &lo2, &hi2);
     const int lo = max(lo1, lo2), hi = min(hi1, hi2);
-    const float *__restrict__ src = c.ypr ? u : ut;
-    const long long NN = (long long)N * N;
+    const float *__restrict__ src = c.ypr ? up : utp;
     long long Fo = c.F0o + (long long)lo * c.dFo;
     long long Fz = F0z + (long long)lo * dFz;
+    // element offset of tap (iz, s, io): (iz + kPad) Np2 + (s + kPad) Np + io + kPad
+    int srow = (lo + kPad) * Np + kPad * Np2 + kPad;
     float acc = 0.f;
-    for (int s = lo; s <= hi; ++s, Fo += c.dFo, Fz += dFz) {
+    for (int s = lo; s <= hi; ++s, Fo += c.dFo, Fz += dFz, srow += Np) {
         const int io = fx40_int(Fo), iz = fx40_int(Fz);
         const float wo = fx40_frac(Fo), wz = fx40_frac(Fz);
-        const bool o0 = (unsigned)io < (unsigned)N, o1 = (unsigned)(io + 1) < (unsigned)N;
-        const bool z0 = (unsigned)iz < (unsigned)N, z1 = (unsigned)(iz + 1) < (unsigned)N;
-        const long long base = ((long long)iz * N + s) * N + io;
-        float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
-        if (z0 && o0) v00 = src[base];
-        if (z0 && o1) v01 = src[base + 1];
-        if (z1 && o0) v10 = src[base + NN];
-        if (z1 && o1) v11 = src[base + NN + 1];
+        const int e = srow + iz * Np2 + io;
+        const float v00 = src[e], v01 = src[e + 1];
+        const float v10 = src[e + Np2], v11 = src[e + Np2 + 1];
         acc += (1.f - wz) * ((1.f - wo) * v00 + wo * v01) + wz * ((1.f - wo) * v10 + wo * v11);
     }
     z[((size_t)j * g.Nv + b) * g.Nu + a] = acc * cone_step(g, c, b);
@@ -271,10 +316,12 @@ __device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__res
 constexpr int kZc = 16;
 
 __global__ __launch_bounds__(256) void k_cone_bp(ConeDev g, const float *__restrict__ rs,
-                                                 float *__restrict__ v) {
-    const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int z0 = blockIdx.z * kZc;
+                                                 float *__restrict__ v, int nbx, int nby) {
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb < 0) return;
+    const int ix = (lb % nbx) * 64 + (threadIdx.x & 63);
+    const int iy = ((lb / nbx) % nby) * 4 + (threadIdx.x >> 6);
+    const int z0 = (lb / (nbx * nby)) * kZc;
     if (ix >= g.N || iy >= g.N) return;
     float acc[kZc];
 #pragma unroll
@@ -301,15 +348,15 @@ __global__ __launch_bounds__(256) void k_cone_bp_at(ConeDev g, const float *__re
 // ----------------------------------------------------------- host wrappers
 void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
     const ConeDev d = hd->cone();
-    const float *ut = u;
-    if (hd->any_x) {
-        hipLaunchKernelGGL(k_transpose_xy, dim3((unsigned)cdiv(d.N, 32), (unsigned)cdiv(d.N, 32), d.N),
-                           dim3(256), 0, s, u, hd->ut.as<float>(), d.N);
-        INRCT_CHECK_LAUNCH();
-        ut = hd->ut.as<float>();
-    }
-    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)cdiv(d.Nu, 64), (unsigned)cdiv(d.Nv, 4), d.V),
-                       dim3(256), 0, s, d, u, ut, z);
+    const size_t Np = (size_t)d.N + 2 * kPad;
+    float *up = hd->ut.as<float>();
+    float *utp = hd->any_x ? up + Np * Np * Np : up;
+    hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)cdiv(d.N, 32), (unsigned)cdiv(d.N, 32), d.N),
+                       dim3(256), 0, s, u, up, hd->any_x ? utp : nullptr, d.N);
+    INRCT_CHECK_LAUNCH();
+    const int ncx = (int)cdiv(d.Nu, 64), ncy = (int)cdiv(d.Nv, 4);
+    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ncy * d.V)), dim3(256), 0, s, d, up, utp, z,
+                       ncx, ncy);
     INRCT_CHECK_LAUNCH();
 }
 
@@ -325,9 +372,9 @@ static const float *cone_prescale(inrct_geom *hd, const float *r, hipStream_t s)
 void cone_backproject(inrct_geom *hd, const float *r, float *v, hipStream_t s) {
     const float *rs = cone_prescale(hd, r, s);
     const ConeDev d = hd->cone();
-    hipLaunchKernelGGL(k_cone_bp, dim3((unsigned)cdiv(d.N, 64), (unsigned)cdiv(d.N, 4),
-                                       (unsigned)cdiv(d.N, kZc)),
-                       dim3(256), 0, s, d, rs, v);
+    const int nbx = (int)cdiv(d.N, 64), nby = (int)cdiv(d.N, 4), nbz = (int)cdiv(d.N, kZc);
+    hipLaunchKernelGGL(k_cone_bp, dim3((unsigned)(nbx * nby * nbz)), dim3(256), 0, s, d, rs, v,
+                       nbx, nby);
     INRCT_CHECK_LAUNCH();
 }
 
