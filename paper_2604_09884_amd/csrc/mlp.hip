@@ -571,9 +571,13 @@ __global__ __launch_bounds__(256) void k_eval_lds(MlpDev m, int n, int ntiles, i
         ring_issue<W>(gfrag, fill_src, ring, fill_slot, wave, lane);
         fill_src = fill_src + 1 == nchunks ? 0 : fill_src + 1;
         fill_slot = fill_slot + 1 == kRingNB ? 0 : fill_slot + 1;
-        const bf16x8 *p = (const bf16x8 *)(ring + slot * RC::CHUNK);
+        // read the ring through an address the compiler cannot trace (the
+        // copies into it are invisible to it), keeping reads after the barrier
+        unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring +
+                       (unsigned)(slot * RC::CHUNK);
+        asm volatile("" : "+v"(off));
         slot = slot + 1 == kRingNB ? 0 : slot + 1;
-        return p;
+        return (const bf16x8 *)(__attribute__((address_space(3))) const bf16x8 *)(size_t)off;
     };
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -693,41 +697,66 @@ __global__ __launch_bounds__(256) void k_eval_lds(MlpDev m, int n, int ntiles, i
 // layer's inputs; a hidden-layer chunk is two k-steps x four M-tiles (the
 // 18th k-step of each half is padding and is not computed).  Layer 1 keeps
 // all eight M-tiles live (its B operands are generated per k-step).
+// Width-256 ring: a chunk is 16 fragments (16 KB): two k-steps of layer 1
+// (eight M-tiles each) or four k-steps of a hidden-layer half (four
+// M-tiles each).  Each wave copies four fragments per chunk; kRingHD chunks
+// are in flight.
+constexpr int kRingHD = 5;
+constexpr int kRingHNB = kRingHD + 1;
+constexpr int kChunkH = 16 * 1024;
+
 struct RingState {
     char *ring;
     const char *gfrag;
     int slot, fill_slot, fill_src, nchunks, wave, lane;
+    __device__ __forceinline__ void issue(int src, int dst_slot) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = wave * 4 + i;
+            dma16(gfrag + ((size_t)src * 16 + f) * 1024 + lane * 16,
+                  ring + dst_slot * kChunkH + f * 1024);
+        }
+    }
     __device__ __forceinline__ const bf16x8 *next() {
-        ring_wait<256>();
+        // all but this wave's copies of the next kRingHD - 1 chunks have landed
+        asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
         __syncthreads();
-        ring_issue<256>(gfrag, fill_src, ring, fill_slot, wave, lane);
+        issue(fill_src, fill_slot);
         fill_src = fill_src + 1 == nchunks ? 0 : fill_src + 1;
-        fill_slot = fill_slot + 1 == kRingNB ? 0 : fill_slot + 1;
-        const bf16x8 *p = (const bf16x8 *)(ring + slot * RingCfg<256>::CHUNK);
-        slot = slot + 1 == kRingNB ? 0 : slot + 1;
-        return p;
+        fill_slot = fill_slot + 1 == kRingHNB ? 0 : fill_slot + 1;
+        // The ring is written only by the copies issued from inline assembly,
+        // which the compiler cannot see; reading it through an address it
+        // cannot trace keeps every read after the wait and barrier above.
+        unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring +
+                       (unsigned)(slot * kChunkH);
+        asm volatile("" : "+v"(off));
+        slot = slot + 1 == kRingHNB ? 0 : slot + 1;
+        return (const bf16x8 *)(__attribute__((address_space(3))) const bf16x8 *)(size_t)off;
     }
 };
 
 // One half (four M-tiles) of a width-256 hidden layer: acc = W_half [bin; 1].
+// Five chunks of four k-steps; k-steps 17..19 are padding and not computed.
 template <int HALF>
 __device__ __forceinline__ void half_gemm(RingState &rs, const bf16x8 (&bin)[2][16],
                                           const bf16x8 &one_b, f32x16 (&acc)[2][4], int lane) {
 #pragma unroll
-    for (int pair = 0; pair <= 8; ++pair) {
+    for (int c = 0; c < 5; ++c) {
         const bf16x8 *A = rs.next();
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int s = 2 * pair + j;
+        for (int j = 0; j < 4; ++j) {
+            const int s = 4 * c + j;
             if (s > 16) continue;
+            bf16x8 af[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) af[mt] = A[(j * 4 + mt) * 64 + lane];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const bf16x8 a = A[(j * 4 + mt) * 64 + lane];
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
                     acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        a, s < 16 ? bin[nt][s] : one_b, s == 0 ? (f32x16){0} : acc[nt][mt], 0, 0,
-                        0);
+                        af[mt], s < 16 ? bin[nt][s] : one_b, s == 0 ? (f32x16){0} : acc[nt][mt],
+                        0, 0, 0);
             }
         }
     }
@@ -758,28 +787,120 @@ __device__ __forceinline__ void half_out(const f32x16 (&acc)[2][4], const float 
                                 act_bf<ACT>(acc[nt][mt][r], w0), fout[nt]);
 }
 
+// Fourier features of k-step s (eight features: four frequencies, sin and
+// cos) of the two 32-point column tiles, as the B operand of layer 1.  sB4
+// holds each frequency row as (bx, by, bz, 0), bz = 0 in 2-D.
+__device__ __forceinline__ void ffn_rows(const float4 *sB4, int s, int h, float4 (&bq)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq[q] = sB4[8 * s + 4 * h + q];
+}
+
+__device__ __forceinline__ void ffn_eval(const float4 (&bq)[4], const float (&xc)[2][3],
+                                         bf16x8 (&b)[2]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const float t =
+                fmaf(bq[q].z, xc[nt][2], fmaf(bq[q].y, xc[nt][1], bq[q].x * xc[nt][0]));
+            const float r = __builtin_amdgcn_fractf(t);
+            b[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
+            b[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
+        }
+    }
+}
+
+__device__ __forceinline__ void ffn_features(const float4 *sB4, int s, int h,
+                                             const float (&xc)[2][3], bf16x8 (&b)[2]) {
+    float4 bq[4];
+    ffn_rows(sB4, s, h, bq);
+    ffn_eval(bq, xc, b);
+}
+
+__device__ __forceinline__ void load_frags8(const bf16x8 *A, int lane, bf16x8 (&af)[8]) {
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) af[mt] = A[mt * 64 + lane];
+}
+
+// One k-step of layer 1 over all eight M-tiles.
+__device__ __forceinline__ void layer1_mfma(const bf16x8 (&af)[8], const bf16x8 (&b)[2],
+                                            f32x16 (&acc)[2][8]) {
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mt], b[nt], acc[nt][mt], 0, 0, 0);
+}
+
+// One k-step of layer 1 with the features of a later k-step computed in
+// between: after the two products of M-tile mt come the sine and cosine of
+// frequency mt / 2 for column tile mt % 2, so the vector unit works while
+// the matrix core does.
+__device__ __forceinline__ void layer1_mfma_feat(const bf16x8 (&af)[8], const bf16x8 (&b)[2],
+                                                 f32x16 (&acc)[2][8], const float4 (&bq)[4],
+                                                 const float (&xc)[2][3], bf16x8 (&nb)[2]) {
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mt], b[nt], acc[nt][mt], 0, 0, 0);
+        const int q = mt >> 1, nt = mt & 1;
+        const float t = fmaf(bq[q].z, xc[nt][2], fmaf(bq[q].y, xc[nt][1], bq[q].x * xc[nt][0]));
+        const float r = __builtin_amdgcn_fractf(t);
+        nb[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
+        nb[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// FOV rank -> grid index (as fov_rank_to_index) with the row tables in LDS;
+// the grid side N is at most kFovLdsN.
+constexpr int kFovLdsN = 2048;
+__device__ __forceinline__ int fov_decode_lds(const int32_t *sRow, const int32_t *sXlo, int N,
+                                              int n_slice, int q, int *ox, int *oy, int *oz) {
+    const int z = q / n_slice;
+    const int rem = q - z * n_slice;
+    int lo = 0, hi = N;  // last y with row_start[y] <= rem
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sRow[mid] <= rem) lo = mid; else hi = mid;
+    }
+    const int x = sXlo[lo] + (rem - sRow[lo]);
+    *ox = x;
+    *oy = lo;
+    *oz = z;
+    return (z * N + lo) * N + x;
+}
+
 template <int ACT>
 __global__ __launch_bounds__(256) void k_eval_lds_h(MlpDev m, int n, int ntiles, int nchunks,
                                                     const char *__restrict__ gfrag,
                                                     float *__restrict__ u) {
     constexpr int MT = 8, NT = 2, NS = 16;
-    __shared__ __attribute__((aligned(16))) char ring[kRingNB * RingCfg<256>::CHUNK];
-    __shared__ float sB[3 * 512];
+    __shared__ __attribute__((aligned(16))) char ring[kRingHNB * kChunkH];
+    __shared__ float4 sB4[512];
     __shared__ float sWout[256];
+    __shared__ int32_t sRow[kFovLdsN + 1], sXlo[kFovLdsN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
     if constexpr (ACT == INRCT_FFN) {
-        for (int i = threadIdx.x; i < m.F * m.d; i += 256) sB[i] = m.B[i];
+        for (int f = threadIdx.x; f < m.F; f += 256)
+            sB4[f] = make_float4(m.B[f * m.d], m.B[f * m.d + 1], m.d == 3 ? m.B[f * m.d + 2] : 0.f,
+                                 0.f);
     }
     for (int i = threadIdx.x; i < 256; i += 256) sWout[i] = m.w_out[i];
+    // the FOV row tables, so that decoding a tile's ranks reads no global memory
+    for (int i = threadIdx.x; i <= m.fov.N; i += 256) sRow[i] = m.fov.row_start[i];
+    for (int i = threadIdx.x; i < m.fov.N; i += 256) sXlo[i] = m.fov.xlo[i];
+    __syncthreads();
     const float b_out = m.b_out[0];
     const float w0 = m.omega0;
     bf16x8 one_b;
 #pragma unroll
     for (int p = 0; p < 8; ++p) one_b[p] = (__bf16)((h == 0 && p == 0) ? 1.f : 0.f);
 
-    RingState rs{ring, gfrag, 0, kRingD % kRingNB, kRingD % nchunks, nchunks, wave, lane};
+    RingState rs{ring, gfrag, 0, kRingHD % kRingHNB, kRingHD % nchunks, nchunks, wave, lane};
 #pragma unroll
-    for (int i = 0; i < kRingD; ++i) ring_issue<256>(gfrag, i % nchunks, ring, i, wave, lane);
+    for (int i = 0; i < kRingHD; ++i) rs.issue(i % nchunks, i);
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         float xc[NT][3];
@@ -791,7 +912,7 @@ __global__ __launch_bounds__(256) void k_eval_lds_h(MlpDev m, int n, int ntiles,
             const bool ok = q < n;
             if (!ok) q = n - 1;
             int ix, iy, iz;
-            gidx[nt] = (int)fov_rank_to_index(m.fov, q, &ix, &iy, &iz);
+            gidx[nt] = fov_decode_lds(sRow, sXlo, m.fov.N, m.fov.n_slice, q, &ix, &iy, &iz);
             if (!ok) gidx[nt] = -1;
             xc[nt][0] = grid_coord(ix, m.fov.N);
             xc[nt][1] = grid_coord(iy, m.fov.N);
@@ -806,37 +927,43 @@ __global__ __launch_bounds__(256) void k_eval_lds_h(MlpDev m, int n, int ntiles,
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
             if constexpr (ACT == INRCT_FFN) {
+                // k-steps before the bias step, in pairs (one chunk each); the
+                // last chunk holds the odd k-step, if any, and the bias step.
+                // The features of the next pair are computed while this
+                // pair's products run (the index is clamped on the last pair,
+                // whose extra features go unused).
                 const int KS1 = m.F / 8;
-                for (int s = 0; s <= KS1; ++s) {
-                    bf16x8 b[NT];
-                    if (s < KS1) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int f = 8 * s + 4 * h + q;
-                            const float bx = sB[f * m.d], by = sB[f * m.d + 1];
-                            const float bz = m.d == 3 ? sB[f * m.d + 2] : 0.f;
-#pragma unroll
-                            for (int nt = 0; nt < NT; ++nt) {
-                                const float t = fmaf(bz, xc[nt][2], fmaf(by, xc[nt][1], bx * xc[nt][0]));
-                                const float r = __builtin_amdgcn_fractf(t);
-                                b[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
-                                b[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) b[nt] = one_b;
-                    }
+                bf16x8 b0[NT], b1[NT];
+                ffn_features(sB4, 0, h, xc, b0);
+                ffn_features(sB4, min(1, KS1 - 1), h, xc, b1);
+                for (int c = 0; c < KS1 / 2; ++c) {
                     const bf16x8 *A = rs.next();
+                    bf16x8 a0[MT], a1[MT], n0[NT], n1[NT];
+                    float4 q0[4], q1[4];
+                    load_frags8(A, lane, a0);
+                    load_frags8(A + MT * 64, lane, a1);
+                    ffn_rows(sB4, min(2 * c + 2, KS1 - 1), h, q0);
+                    ffn_rows(sB4, min(2 * c + 3, KS1 - 1), h, q1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    layer1_mfma_feat(a0, b0, acc, q0, xc, n0);
+                    layer1_mfma_feat(a1, b1, acc, q1, xc, n1);
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        const bf16x8 a = A[mt * 64 + lane];
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                a, b[nt], acc[nt][mt], 0, 0, 0);
+                    for (int nt = 0; nt < NT; ++nt) {
+                        b0[nt] = n0[nt];
+                        b1[nt] = n1[nt];
                     }
                 }
+                const bf16x8 *A = rs.next();
+                bf16x8 af[MT];
+                if (KS1 % 2) {
+                    // b0 holds the features of k-step KS1 - 1
+                    load_frags8(A, lane, af);
+                    layer1_mfma(af, b0, acc);
+                    A += MT * 64;
+                }
+                const bf16x8 bb[NT] = {one_b, one_b};
+                load_frags8(A, lane, af);
+                layer1_mfma(af, bb, acc);
             } else {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
@@ -1231,12 +1358,13 @@ void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u
                     hipStream_t s) {
     const MlpDev d = make_dev(m, theta, B);
     const bool lds_path = m->bf16() && (m->arch.kind != INRCT_FFN || m->arch.n_freq <= 512) &&
-                          (m->arch.kind == INRCT_FFN || m->arch.depth >= 2);
+                          (m->arch.kind == INRCT_FFN || m->arch.depth >= 2) &&
+                          m->N <= kFovLdsN;
     if (lds_path) {
         if (m->arch.width == 256) {
             const long long ntiles = cdiv(m->n_fov, 256);
             const long long grid = std::min<long long>(ntiles, m->n_cu);
-            const int nchunks = (int)(m->nfrag_h / 8);
+            const int nchunks = (int)(m->nfrag_h / 16);
             if (m->arch.kind == INRCT_FFN)
                 hipLaunchKernelGGL(k_eval_lds_h<INRCT_FFN>, dim3((unsigned)grid), dim3(256), 0, s,
                                    d, (int)m->n_fov, (int)ntiles, nchunks,
@@ -1400,23 +1528,25 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
                 // (8 M-tiles), hidden layers by half, then k-step pairs x 4 M-tiles
                 std::vector<int> hl, hm, hs;
                 if (a.kind == INRCT_FFN) {
+                    // layer 1: pairs of k-steps (the last pair padded)
                     const int KS1 = ksteps(layer_K(a.kind, a.n_freq, d, W, 1), 16);
-                    for (int s = 0; s < KS1; ++s)
+                    const int KS1p = (KS1 + 1) / 2 * 2;
+                    for (int s = 0; s < KS1p; ++s)
                         for (int mt = 0; mt < 8; ++mt) {
                             hl.push_back(1);
                             hm.push_back(mt);
                             hs.push_back(s);
                         }
                 }
+                // hidden layers: per half, 20 k-steps (17 real) x 4 M-tiles
                 for (int l = 2; l <= L; ++l)
                     for (int half = 0; half < 2; ++half)
-                        for (int pr = 0; pr <= 8; ++pr)
-                            for (int j = 0; j < 2; ++j)
-                                for (int mt = 0; mt < 4; ++mt) {
-                                    hl.push_back(l);
-                                    hm.push_back(half * 4 + mt);
-                                    hs.push_back(2 * pr + j);
-                                }
+                        for (int s = 0; s < 20; ++s)
+                            for (int mt = 0; mt < 4; ++mt) {
+                                hl.push_back(l);
+                                hm.push_back(half * 4 + mt);
+                                hs.push_back(s);
+                            }
                 m->nfrag_h = (long long)hl.size();
                 upload(m->pkh_layer, hl);
                 upload(m->pkh_mt, hm);
