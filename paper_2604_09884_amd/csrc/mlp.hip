@@ -44,6 +44,8 @@ struct MlpDev {
     const float *B;      // FFN Fourier matrix [F][d]
     long long off[kMaxDepth + 2];   // fragment offset of layer l (1-based)
     long long offT[kMaxDepth + 2];
+    const float *theta;             // parameters (for the biases)
+    long long boff[kMaxDepth + 2];  // theta offset of the bias of layer l (1-based)
     FovDev fov;
 };
 
@@ -692,20 +694,21 @@ __global__ __launch_bounds__(256) void k_eval_lds(MlpDev m, int n, int ntiles, i
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// Width-256 variant: hidden layers produce their 256 outputs in two halves
-// of four M-tiles, so only half the accumulators are live next to the
-// layer's inputs; a hidden-layer chunk is two k-steps x four M-tiles (the
-// 18th k-step of each half is padding and is not computed).  Layer 1 keeps
-// all eight M-tiles live (its B operands are generated per k-step).
-// Width-256 ring: a chunk is 16 fragments (16 KB): two k-steps of layer 1
-// (eight M-tiles each) or four k-steps of a hidden-layer half (four
-// M-tiles each).  Each wave copies four fragments per chunk; kRingHD chunks
-// are in flight.
-constexpr int kRingHD = 5;
-constexpr int kRingHNB = kRingHD + 1;
-constexpr int kChunkH = 16 * 1024;
+// ------------------------------------------------------------------------
+// Width-256 BF16 grid evaluation.  A workgroup of eight waves (two per SIMD)
+// evaluates a tile of 256 FOV points, one 32-point column tile per wave.  The
+// weights stream through a ring of 32 KB chunks in LDS (copied straight from
+// global memory to LDS); a chunk is four k-steps of layer 1 (eight M-tiles)
+// or eight k-steps of one half (four M-tiles) of a hidden layer.  Every
+// fragment read from LDS feeds one product per wave; two waves per SIMD hide
+// each other's LDS, barrier and vector-unit time.  Biases initialise the
+// accumulators (from LDS), so no k-step carries them and no chunk is padded.
+constexpr int kRingWD = 3;                 // chunks in flight
+constexpr int kRingWNB = kRingWD + 1;      // ring slots
+constexpr int kChunkW = 32 * 1024;
+constexpr int kFovLdsN = 1024;             // largest grid side of the LDS path
 
-struct RingState {
+struct RingW {
     char *ring;
     const char *gfrag;
     int slot, fill_slot, fill_src, nchunks, wave, lane;
@@ -713,149 +716,120 @@ struct RingState {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int f = wave * 4 + i;
-            dma16(gfrag + ((size_t)src * 16 + f) * 1024 + lane * 16,
-                  ring + dst_slot * kChunkH + f * 1024);
+            dma16(gfrag + ((size_t)src * 32 + f) * 1024 + lane * 16,
+                  ring + dst_slot * kChunkW + f * 1024);
         }
     }
+    // Waits for the next chunk, then refills the slot every wave has finished
+    // with (the barrier orders this wave's refill after the other waves'
+    // reads of it and publishes the other waves' copies of the next chunk).
     __device__ __forceinline__ const bf16x8 *next() {
-        // all but this wave's copies of the next kRingHD - 1 chunks have landed
-        asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+        // all but this wave's copies of the next kRingWD - 1 chunks have landed
+        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
         __syncthreads();
         issue(fill_src, fill_slot);
         fill_src = fill_src + 1 == nchunks ? 0 : fill_src + 1;
-        fill_slot = fill_slot + 1 == kRingHNB ? 0 : fill_slot + 1;
-        // The ring is written only by the copies issued from inline assembly,
-        // which the compiler cannot see; reading it through an address it
-        // cannot trace keeps every read after the wait and barrier above.
+        fill_slot = fill_slot + 1 == kRingWNB ? 0 : fill_slot + 1;
+        // read the ring through an address the compiler cannot trace, so no
+        // read is hoisted above the wait and barrier (the copies are asm)
         unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring +
-                       (unsigned)(slot * kChunkH);
+                       (unsigned)(slot * kChunkW);
         asm volatile("" : "+v"(off));
-        slot = slot + 1 == kRingHNB ? 0 : slot + 1;
+        slot = slot + 1 == kRingWNB ? 0 : slot + 1;
         return (const bf16x8 *)(__attribute__((address_space(3))) const bf16x8 *)(size_t)off;
     }
 };
 
-// One half (four M-tiles) of a width-256 hidden layer: acc = W_half [bin; 1].
-// Five chunks of four k-steps; k-steps 17..19 are padding and not computed.
-template <int HALF>
-__device__ __forceinline__ void half_gemm(RingState &rs, const bf16x8 (&bin)[2][16],
-                                          const bf16x8 &one_b, f32x16 (&acc)[2][4], int lane) {
+__device__ __forceinline__ void load_frags4(const bf16x8 *A, int j, int lane, bf16x8 (&af)[4]) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        const bf16x8 *A = rs.next();
+    for (int mt = 0; mt < 4; ++mt) af[mt] = A[(j * 4 + mt) * 64 + lane];
+}
+
+__device__ __forceinline__ void load_frags8(const bf16x8 *A, int j, int lane, bf16x8 (&af)[8]) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int s = 4 * c + j;
-            if (s > 16) continue;
-            bf16x8 af[4];
+    for (int mt = 0; mt < 8; ++mt) af[mt] = A[(j * 8 + mt) * 64 + lane];
+}
+
+// Accumulator rows of M-tile mt for this lane (crow order) from a bias row
+// of 256 floats in LDS: four runs of four consecutive outputs.
+__device__ __forceinline__ f32x16 bias_tile(const float *sb, int mt, int h) {
+    f32x16 a;
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = A[(j * 4 + mt) * 64 + lane];
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        af[mt], s < 16 ? bin[nt][s] : one_b, s == 0 ? (f32x16){0} : acc[nt][mt],
-                        0, 0, 0);
-            }
-        }
+    for (int j = 0; j < 4; ++j) {
+        const float4 v = *(const float4 *)(sb + 32 * mt + 8 * j + 4 * h);
+        a[4 * j] = v.x;
+        a[4 * j + 1] = v.y;
+        a[4 * j + 2] = v.z;
+        a[4 * j + 3] = v.w;
     }
+    return a;
 }
 
-template <int ACT, int HALF>
-__device__ __forceinline__ void half_to_b(const f32x16 (&acc)[2][4], bf16x8 (&out)[2][8],
-                                          float w0) {
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int so = 0; so < 8; ++so)
-#pragma unroll
-            for (int p = 0; p < 8; ++p)
-                out[nt][so][p] = (__bf16)act_bf<ACT>(acc[nt][so / 2][8 * (so % 2) + p], w0);
-}
-
-template <int ACT, int HALF>
-__device__ __forceinline__ void half_out(const f32x16 (&acc)[2][4], const float *sWout, int h,
-                                         float (&fout)[2], float w0) {
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                fout[nt] = fmaf(sWout[32 * (HALF * 4 + mt) + crow(r, h)],
-                                act_bf<ACT>(acc[nt][mt][r], w0), fout[nt]);
-}
-
-// Fourier features of k-step s (eight features: four frequencies, sin and
-// cos) of the two 32-point column tiles, as the B operand of layer 1.  sB4
-// holds each frequency row as (bx, by, bz, 0), bz = 0 in 2-D.
+// Frequency rows of layer-1 k-step s for this lane's half h: four rows
+// (bx, by, bz, 0), bz = 0 in 2-D.
 __device__ __forceinline__ void ffn_rows(const float4 *sB4, int s, int h, float4 (&bq)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) bq[q] = sB4[8 * s + 4 * h + q];
 }
 
-__device__ __forceinline__ void ffn_eval(const float4 (&bq)[4], const float (&xc)[2][3],
-                                         bf16x8 (&b)[2]) {
+__device__ __forceinline__ void ffn_feat1(const float4 (&bq)[4], const float (&xc)[3],
+                                          bf16x8 &b) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const float t =
-                fmaf(bq[q].z, xc[nt][2], fmaf(bq[q].y, xc[nt][1], bq[q].x * xc[nt][0]));
-            const float r = __builtin_amdgcn_fractf(t);
-            b[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
-            b[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
-        }
+        const float t = fmaf(bq[q].z, xc[2], fmaf(bq[q].y, xc[1], bq[q].x * xc[0]));
+        const float r = __builtin_amdgcn_fractf(t);
+        b[2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
+        b[2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
     }
 }
 
-__device__ __forceinline__ void ffn_features(const float4 *sB4, int s, int h,
-                                             const float (&xc)[2][3], bf16x8 (&b)[2]) {
-    float4 bq[4];
-    ffn_rows(sB4, s, h, bq);
-    ffn_eval(bq, xc, b);
-}
-
-__device__ __forceinline__ void load_frags8(const bf16x8 *A, int lane, bf16x8 (&af)[8]) {
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) af[mt] = A[mt * 64 + lane];
-}
-
-// One k-step of layer 1 over all eight M-tiles.
-__device__ __forceinline__ void layer1_mfma(const bf16x8 (&af)[8], const bf16x8 (&b)[2],
-                                            f32x16 (&acc)[2][8]) {
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-            acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mt], b[nt], acc[nt][mt], 0, 0, 0);
-}
-
-// One k-step of layer 1 with the features of a later k-step computed in
-// between: after the two products of M-tile mt come the sine and cosine of
-// frequency mt / 2 for column tile mt % 2, so the vector unit works while
-// the matrix core does.
-__device__ __forceinline__ void layer1_mfma_feat(const bf16x8 (&af)[8], const bf16x8 (&b)[2],
-                                                 f32x16 (&acc)[2][8], const float4 (&bq)[4],
-                                                 const float (&xc)[2][3], bf16x8 (&nb)[2]) {
+// Layer-1 k-step for one column tile with the features of the following
+// k-step computed between the products (frequency mt / 2 after odd mt).
+__device__ __forceinline__ void layer1_w(const bf16x8 (&af)[8], const bf16x8 &b, f32x16 (&acc)[8],
+                                         const float4 (&bq)[4], const float (&xc)[3],
+                                         bf16x8 &nb) {
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-            acc[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mt], b[nt], acc[nt][mt], 0, 0, 0);
-        const int q = mt >> 1, nt = mt & 1;
-        const float t = fmaf(bq[q].z, xc[nt][2], fmaf(bq[q].y, xc[nt][1], bq[q].x * xc[nt][0]));
-        const float r = __builtin_amdgcn_fractf(t);
-        nb[nt][2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
-        nb[nt][2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mt], b, acc[mt], 0, 0, 0);
+        if (mt & 1) {
+            const int q = mt >> 1;
+            const float t = fmaf(bq[q].z, xc[2], fmaf(bq[q].y, xc[1], bq[q].x * xc[0]));
+            const float r = __builtin_amdgcn_fractf(t);
+            nb[2 * q] = (__bf16)__builtin_amdgcn_sinf(r);
+            nb[2 * q + 1] = (__bf16)__builtin_amdgcn_cosf(r);
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// FOV rank -> grid index (as fov_rank_to_index) with the row tables in LDS;
-// the grid side N is at most kFovLdsN.
-constexpr int kFovLdsN = 2048;
+// One hidden-layer half (four M-tiles) for one column tile: sixteen k-steps
+// in two chunks, fragments read one k-step ahead; the second chunk's
+// barrier comes before the first chunk's last products.
+template <int HALF>
+__device__ __forceinline__ void half_gemm_w(RingW &rs, const bf16x8 (&bin)[16], const float *sb,
+                                            int h, f32x16 (&acc)[4], int lane) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = bias_tile(sb, 4 * HALF + mt, h);
+    const bf16x8 *A = rs.next();
+    bf16x8 cur[4], nxt[4];
+    load_frags4(A, 0, lane, cur);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        if (s + 1 < 16) {
+            if ((s + 1) % 8 == 0) A = rs.next();
+            load_frags4(A, (s + 1) % 8, lane, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[mt], bin[s], acc[mt], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) cur[mt] = nxt[mt];
+    }
+}
+
+// FOV rank -> grid index (as fov_rank_to_index) with the row tables in LDS.
 __device__ __forceinline__ int fov_decode_lds(const int32_t *sRow, const int32_t *sXlo, int N,
                                               int n_slice, int q, int *ox, int *oy, int *oz) {
     const int z = q / n_slice;
@@ -873,177 +847,170 @@ __device__ __forceinline__ int fov_decode_lds(const int32_t *sRow, const int32_t
 }
 
 template <int ACT>
-__global__ __launch_bounds__(256) void k_eval_lds_h(MlpDev m, int n, int ntiles, int nchunks,
+__global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles, int nchunks,
                                                     const char *__restrict__ gfrag,
                                                     float *__restrict__ u) {
-    constexpr int MT = 8, NT = 2, NS = 16;
-    __shared__ __attribute__((aligned(16))) char ring[kRingHNB * kChunkH];
+    constexpr int MT = 8, NS = 16;
+    __shared__ __attribute__((aligned(16))) char ring[kRingWNB * kChunkW];
     __shared__ float4 sB4[512];
+    __shared__ __attribute__((aligned(16))) float sBias[kMaxDepth * 256];
     __shared__ float sWout[256];
     __shared__ int32_t sRow[kFovLdsN + 1], sXlo[kFovLdsN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
     if constexpr (ACT == INRCT_FFN) {
-        for (int f = threadIdx.x; f < m.F; f += 256)
+        for (int f = threadIdx.x; f < m.F; f += 512)
             sB4[f] = make_float4(m.B[f * m.d], m.B[f * m.d + 1], m.d == 3 ? m.B[f * m.d + 2] : 0.f,
                                  0.f);
+    } else {
+        // SIREN layer 1 rows (w_x, w_y, w_z, b), w_z = 0 in 2-D
+        for (int o = threadIdx.x; o < 256; o += 512)
+            sB4[o] = make_float4(m.W1[o * m.d], m.W1[o * m.d + 1],
+                                 m.d == 3 ? m.W1[o * m.d + 2] : 0.f, m.b1[o]);
     }
-    for (int i = threadIdx.x; i < 256; i += 256) sWout[i] = m.w_out[i];
+    for (int i = threadIdx.x; i < m.L * 256; i += 512)
+        sBias[i] = m.theta[m.boff[1 + i / 256] + i % 256];
+    for (int i = threadIdx.x; i < 256; i += 512) sWout[i] = m.w_out[i];
     // the FOV row tables, so that decoding a tile's ranks reads no global memory
-    for (int i = threadIdx.x; i <= m.fov.N; i += 256) sRow[i] = m.fov.row_start[i];
-    for (int i = threadIdx.x; i < m.fov.N; i += 256) sXlo[i] = m.fov.xlo[i];
+    for (int i = threadIdx.x; i <= m.fov.N; i += 512) sRow[i] = m.fov.row_start[i];
+    for (int i = threadIdx.x; i < m.fov.N; i += 512) sXlo[i] = m.fov.xlo[i];
     __syncthreads();
     const float b_out = m.b_out[0];
     const float w0 = m.omega0;
-    bf16x8 one_b;
-#pragma unroll
-    for (int p = 0; p < 8; ++p) one_b[p] = (__bf16)((h == 0 && p == 0) ? 1.f : 0.f);
 
-    RingState rs{ring, gfrag, 0, kRingHD % kRingHNB, kRingHD % nchunks, nchunks, wave, lane};
+    RingW rs{ring, gfrag, 0, kRingWD % kRingWNB, kRingWD % nchunks, nchunks, wave, lane};
 #pragma unroll
-    for (int i = 0; i < kRingHD; ++i) rs.issue(i % nchunks, i);
+    for (int i = 0; i < kRingWD; ++i) rs.issue(i % nchunks, i);
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        float xc[NT][3];
-        int gidx[NT];
-        const int base = tile * 256 + wave * 64;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            int q = base + nt * 32 + (lane & 31);
+        float xc[3];
+        int gidx;
+        {
+            int q = tile * 256 + wave * 32 + (lane & 31);
             const bool ok = q < n;
             if (!ok) q = n - 1;
             int ix, iy, iz;
-            gidx[nt] = fov_decode_lds(sRow, sXlo, m.fov.N, m.fov.n_slice, q, &ix, &iy, &iz);
-            if (!ok) gidx[nt] = -1;
-            xc[nt][0] = grid_coord(ix, m.fov.N);
-            xc[nt][1] = grid_coord(iy, m.fov.N);
-            xc[nt][2] = m.fov.dim == 3 ? grid_coord(iz, m.fov.N) : 0.f;
+            gidx = fov_decode_lds(sRow, sXlo, m.fov.N, m.fov.n_slice, q, &ix, &iy, &iz);
+            if (!ok) gidx = -1;
+            xc[0] = grid_coord(ix, m.fov.N);
+            xc[1] = grid_coord(iy, m.fov.N);
+            xc[2] = m.fov.dim == 3 ? grid_coord(iz, m.fov.N) : 0.f;
         }
-        bf16x8 bin[NT][NS];
+        bf16x8 bin[NS];
         {
             // ---------------- layer 1, all eight M-tiles
-            f32x16 acc[NT][MT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (f32x16){0};
+            f32x16 acc[MT];
             if constexpr (ACT == INRCT_FFN) {
-                // k-steps before the bias step, in pairs (one chunk each); the
-                // last chunk holds the odd k-step, if any, and the bias step.
-                // The features of the next pair are computed while this
-                // pair's products run (the index is clamped on the last pair,
-                // whose extra features go unused).
-                const int KS1 = m.F / 8;
-                bf16x8 b0[NT], b1[NT];
-                ffn_features(sB4, 0, h, xc, b0);
-                ffn_features(sB4, min(1, KS1 - 1), h, xc, b1);
-                for (int c = 0; c < KS1 / 2; ++c) {
-                    const bf16x8 *A = rs.next();
-                    bf16x8 a0[MT], a1[MT], n0[NT], n1[NT];
-                    float4 q0[4], q1[4];
-                    load_frags8(A, lane, a0);
-                    load_frags8(A + MT * 64, lane, a1);
-                    ffn_rows(sB4, min(2 * c + 2, KS1 - 1), h, q0);
-                    ffn_rows(sB4, min(2 * c + 3, KS1 - 1), h, q1);
-                    __builtin_amdgcn_sched_barrier(0);
-                    layer1_mfma_feat(a0, b0, acc, q0, xc, n0);
-                    layer1_mfma_feat(a1, b1, acc, q1, xc, n1);
+                // chunks of four k-steps; fragments one k-step ahead, the next
+                // chunk's barrier before this chunk's last products, features
+                // of the next k-step between the products (the index is
+                // clamped at the end, where the extra features go unused)
+                const int KS1 = m.F / 8;  // a multiple of four here
+                const int nch1 = KS1 / 4;
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        b0[nt] = n0[nt];
-                        b1[nt] = n1[nt];
-                    }
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = bias_tile(sBias, mt, h);
+                bf16x8 b, cur[MT], nxt[MT];
+                {
+                    float4 q0[4];
+                    ffn_rows(sB4, 0, h, q0);
+                    ffn_feat1(q0, xc, b);
                 }
                 const bf16x8 *A = rs.next();
-                bf16x8 af[MT];
-                if (KS1 % 2) {
-                    // b0 holds the features of k-step KS1 - 1
-                    load_frags8(A, lane, af);
-                    layer1_mfma(af, b0, acc);
-                    A += MT * 64;
+                load_frags8(A, 0, lane, cur);
+                for (int c = 0; c < nch1; ++c) {
+                    const bool more = c + 1 < nch1;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int s = 4 * c + j;
+                        if (j < 3) {
+                            load_frags8(A, j + 1, lane, nxt);
+                        } else if (more) {
+                            A = rs.next();
+                            load_frags8(A, 0, lane, nxt);
+                        }
+                        float4 q[4];
+                        ffn_rows(sB4, min(s + 1, KS1 - 1), h, q);
+                        bf16x8 nb;
+                        __builtin_amdgcn_sched_barrier(0);
+                        layer1_w(cur, b, acc, q, xc, nb);
+                        b = nb;
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) cur[mt] = nxt[mt];
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
-                const bf16x8 bb[NT] = {one_b, one_b};
-                load_frags8(A, lane, af);
-                layer1_mfma(af, bb, acc);
             } else {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const int o = 32 * mt + crow(r, h);
-                        const float c0 = m.W1[o * m.d], c1 = m.W1[o * m.d + 1];
-                        const float c2 = m.d == 3 ? m.W1[o * m.d + 2] : 0.f;
-                        const float bb = m.b1[o];
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[nt][mt][r] = fmaf(c2, xc[nt][2], fmaf(c1, xc[nt][1], fmaf(c0, xc[nt][0], bb)));
+                        const float4 c = sB4[32 * mt + crow(r, h)];
+                        acc[mt][r] = fmaf(c.z, xc[2], fmaf(c.y, xc[1], fmaf(c.x, xc[0], c.w)));
                     }
             }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+            for (int s2 = 0; s2 < NS; ++s2)
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
+                for (int p = 0; p < 8; ++p)
+                    bin[s2][p] = (__bf16)act_bf<ACT>(acc[s2 / 2][8 * (s2 % 2) + p], w0);
+        }
+        // ---------------- layers 2..L-1, two halves each
+        for (int l = 2; l < m.L; ++l) {
+            const float *sb = sBias + (l - 1) * 256;
+            bf16x8 lo[8];
+            {
+                f32x16 acc[4];
+                half_gemm_w<0>(rs, bin, sb, h, acc, lane);
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2)
 #pragma unroll
                     for (int p = 0; p < 8; ++p)
-                        bin[nt][s][p] = (__bf16)act_bf<ACT>(acc[nt][s / 2][8 * (s % 2) + p], w0);
-        }
-        // ---------------- layers 2..L-1: two halves each
-        for (int l = 2; l < m.L; ++l) {
-            bf16x8 lo[NT][8], hi[NT][8];
-            {
-                f32x16 acc[NT][4];
-                half_gemm<0>(rs, bin, one_b, acc, lane);
-                half_to_b<ACT, 0>(acc, lo, w0);
+                        lo[s2][p] = (__bf16)act_bf<ACT>(acc[s2 / 2][8 * (s2 % 2) + p], w0);
             }
             {
-                f32x16 acc[NT][4];
-                half_gemm<1>(rs, bin, one_b, acc, lane);
-                half_to_b<ACT, 1>(acc, hi, w0);
+                f32x16 acc[4];
+                half_gemm_w<1>(rs, bin, sb, h, acc, lane);
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+                    for (int p = 0; p < 8; ++p)
+                        bin[8 + s2][p] = (__bf16)act_bf<ACT>(acc[s2 / 2][8 * (s2 % 2) + p], w0);
             }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2) {
-                    bin[nt][s2] = lo[nt][s2];
-                    bin[nt][8 + s2] = hi[nt][s2];
-                }
+            for (int s2 = 0; s2 < 8; ++s2) bin[s2] = lo[s2];
         }
         // ---------------- last hidden layer L and the linear output
-        float fout[NT] = {0.f, 0.f};
+        float fout = 0.f;
         if (m.L >= 2) {
-            {
-                f32x16 acc[NT][4];
-                half_gemm<0>(rs, bin, one_b, acc, lane);
-                half_out<ACT, 0>(acc, sWout, h, fout, w0);
-            }
-            {
-                f32x16 acc[NT][4];
-                half_gemm<1>(rs, bin, one_b, acc, lane);
-                half_out<ACT, 1>(acc, sWout, h, fout, w0);
+            const float *sb = sBias + (m.L - 1) * 256;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                f32x16 acc[4];
+                if (half == 0) half_gemm_w<0>(rs, bin, sb, h, acc, lane);
+                else half_gemm_w<1>(rs, bin, sb, h, acc, lane);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        fout = fmaf(sWout[32 * (4 * half + mt) + crow(r, h)],
+                                    act_bf<ACT>(acc[mt][r], w0), fout);
             }
         } else {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+            for (int s2 = 0; s2 < NS; ++s2)
 #pragma unroll
-                for (int s2 = 0; s2 < NS; ++s2)
-#pragma unroll
-                    for (int p = 0; p < 8; ++p) {
-                        const int r = 8 * (s2 % 2) + p;
-                        fout[nt] = fmaf(sWout[32 * (s2 / 2) + crow(r, h)], (float)bin[nt][s2][p], fout[nt]);
-                    }
+                for (int p = 0; p < 8; ++p) {
+                    const int r = 8 * (s2 % 2) + p;
+                    fout = fmaf(sWout[32 * (s2 / 2) + crow(r, h)], (float)bin[s2][p], fout);
+                }
         }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const float sacc = fout[nt] + __shfl_xor(fout[nt], 32);
-            if (lane < 32 && gidx[nt] >= 0) u[gidx[nt]] = sacc + b_out;
-        }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const float sacc = fout + __shfl_xor(fout, 32);
+        if (lane < 32 && gidx >= 0) u[gidx] = sacc + b_out;
+        // no drain: an older store in flight only makes the next ring wait stricter
     }
+    // the copies of the chunks never consumed land before the wave ends
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// ------------------------------------------------ VJP phase 1: fwd + deltas
-// Points j0 .. j0 + P of the index list form the chunk; column c of the
-// scratch holds point j0 + c (columns past k carry a zero cotangent).
 template <int W, int NT, bool BF, int ACT>
 __global__ __launch_bounds__(256) void k_vjp_tile(MlpDev m, const int32_t *__restrict__ idx,
                                                   long long k, long long j0,
@@ -1278,6 +1245,12 @@ static MlpDev make_dev(const inrct_model *m, const float *theta, const float *B)
         d.off[l] = m->frag_off[l];
         d.offT[l] = m->fragT_off[l];
     }
+    d.theta = theta;
+    for (int l = 0; l < kMaxDepth + 2; ++l) d.boff[l] = 0;
+    for (int l = 1; l <= L; ++l)
+        d.boff[l] = m->loff[l] + (long long)layer_K(m->arch.kind, m->arch.n_freq,
+                                                    m->arch.in_dim, m->arch.width, l) *
+                                     m->arch.width;
     d.fov = m->fov.dev(m->dim);
     return d;
 }
@@ -1357,20 +1330,23 @@ static void launch_eval_lds(const inrct_model *m, const MlpDev &d, float *u, hip
 void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u,
                     hipStream_t s) {
     const MlpDev d = make_dev(m, theta, B);
-    const bool lds_path = m->bf16() && (m->arch.kind != INRCT_FFN || m->arch.n_freq <= 512) &&
+    const bool lds_path = m->bf16() &&
+                          (m->arch.kind != INRCT_FFN ||
+                           (m->arch.n_freq <= 512 &&
+                            (m->arch.width == 128 || m->arch.n_freq % 32 == 0))) &&
                           (m->arch.kind == INRCT_FFN || m->arch.depth >= 2) &&
                           m->N <= kFovLdsN;
     if (lds_path) {
         if (m->arch.width == 256) {
             const long long ntiles = cdiv(m->n_fov, 256);
             const long long grid = std::min<long long>(ntiles, m->n_cu);
-            const int nchunks = (int)(m->nfrag_h / 16);
+            const int nchunks = (int)(m->nfrag_h / 32);
             if (m->arch.kind == INRCT_FFN)
-                hipLaunchKernelGGL(k_eval_lds_h<INRCT_FFN>, dim3((unsigned)grid), dim3(256), 0, s,
+                hipLaunchKernelGGL(k_eval_lds_w<INRCT_FFN>, dim3((unsigned)grid), dim3(512), 0, s,
                                    d, (int)m->n_fov, (int)ntiles, nchunks,
                                    (const char *)m->frag_h.ptr, u);
             else
-                hipLaunchKernelGGL(k_eval_lds_h<INRCT_SIREN>, dim3((unsigned)grid), dim3(256), 0,
+                hipLaunchKernelGGL(k_eval_lds_w<INRCT_SIREN>, dim3((unsigned)grid), dim3(512), 0,
                                    s, d, (int)m->n_fov, (int)ntiles, nchunks,
                                    (const char *)m->frag_h.ptr, u);
             INRCT_CHECK_LAUNCH();
@@ -1524,24 +1500,22 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             }
             m->nfragT = (long long)fl.size() - m->nfrag;
             if (bf && W == 256) {
-                // chunk stream of the width-256 LDS kernel: layer 1 by k-step
-                // (8 M-tiles), hidden layers by half, then k-step pairs x 4 M-tiles
+                // chunk stream of the width-256 LDS kernel (biases excluded):
+                // layer 1 by k-step x 8 M-tiles, hidden layers by half, then
+                // k-step x 4 M-tiles
                 std::vector<int> hl, hm, hs;
                 if (a.kind == INRCT_FFN) {
-                    // layer 1: pairs of k-steps (the last pair padded)
-                    const int KS1 = ksteps(layer_K(a.kind, a.n_freq, d, W, 1), 16);
-                    const int KS1p = (KS1 + 1) / 2 * 2;
-                    for (int s = 0; s < KS1p; ++s)
+                    const int KS1 = ksteps(layer_K(a.kind, a.n_freq, d, W, 1), 16) - 1;
+                    for (int s = 0; s < KS1; ++s)
                         for (int mt = 0; mt < 8; ++mt) {
                             hl.push_back(1);
                             hm.push_back(mt);
                             hs.push_back(s);
                         }
                 }
-                // hidden layers: per half, 20 k-steps (17 real) x 4 M-tiles
                 for (int l = 2; l <= L; ++l)
                     for (int half = 0; half < 2; ++half)
-                        for (int s = 0; s < 20; ++s)
+                        for (int s = 0; s < 16; ++s)
                             for (int mt = 0; mt < 4; ++mt) {
                                 hl.push_back(l);
                                 hm.push_back(half * 4 + mt);
