@@ -129,6 +129,26 @@ def cpu_baseline(p, target_s):
     }
 
 
+def e_kernel_traffic():
+    """HBM bytes per launch of the grid-evaluation kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
+    changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "step_c4_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2604_09884_amd", "csrc", "mlp.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"source sha256: ([0-9a-f]{64})", text)
+    m_b = re.search(r"traffic bytes per launch: (\d+)", text)
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return int(m_b.group(1))
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -184,12 +204,15 @@ def main():
     log("timed %d steps: %.2f ms/step, loss %.6g, stages %s"
         % (a.steps, ms_step, loss, {k_: round(v / a.steps, 3) for k_, v in stages.items()}))
 
+    traffic = e_kernel_traffic() if a.config == "c4" and dtype == "bf16" else None
     flop_per_point = p.arch.flops_forward()
     e_ms = stages["eval_grid"] / a.steps
     achieved = model.n_fov * flop_per_point / (e_ms * 1e-3)
-    roofline = {"bound": "mfma", "kernel": "k_eval_grid (grid evaluation E)",
+    roofline = {"bound": "mfma", "kernel": "k_eval_lds_w (grid evaluation E)",
                 "achieved": achieved / 1e12, "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[dtype], "traffic": None,
+                "frac": achieved / PEAK[dtype], "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated; "
+                                "profiles/step_c4_hbm_traffic.md)",
                 "per_unit": "%d FLOP per FOV point x %d points per launch"
                             % (flop_per_point, model.n_fov),
                 "avg_launch_ms": e_ms}
