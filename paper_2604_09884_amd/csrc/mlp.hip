@@ -540,6 +540,41 @@ __device__ __forceinline__ float act_bf(float z, float w0) {
     else return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(w0 * z * 0.15915494309189535f));
 }
 
+// max(z, 0) in one instruction (no NaN canonicalisation of z first)
+__device__ __forceinline__ float relu1(float z) {
+    float r;
+    asm("v_max_f32 %0, 0, %1" : "=v"(r) : "v"(z));
+    return r;
+}
+
+// Eight accumulator values -> activated BF16 operand.  ReLU is applied after
+// rounding, on the BF16 bit patterns as signed 16-bit integers (negative
+// values, -0 included, have the sign bit set); rounding is monotonic and
+// keeps the sign, so this equals rounding the rectified value.
+template <int ACT>
+__device__ __forceinline__ bf16x8 act_pack8(const f32x16 &a, int base, float w0) {
+    bf16x8 t;
+    if constexpr (ACT == INRCT_FFN) {
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        typedef short s16x2 __attribute__((ext_vector_type(2)));
+        uint4 w;
+        unsigned *wp = (unsigned *)&w;
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) {
+            const f32x2 f = {a[base + 2 * pp], a[base + 2 * pp + 1]};
+            s16x2 q = __builtin_bit_cast(s16x2, __builtin_convertvector(f, bf16x2));
+            q = __builtin_elementwise_max(q, (s16x2)0);
+            wp[pp] = __builtin_bit_cast(unsigned, q);
+        }
+        t = __builtin_bit_cast(bf16x8, w);
+    } else {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) t[p] = (__bf16)act_bf<ACT>(a[base + p], w0);
+    }
+    return t;
+}
+
 template <int W, int ACT>
 __global__ __launch_bounds__(256) void k_eval_lds(MlpDev m, int n, int ntiles, int nchunks,
                                                    float *__restrict__ u) {
@@ -948,10 +983,7 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
                     }
             }
 #pragma unroll
-            for (int s2 = 0; s2 < NS; ++s2)
-#pragma unroll
-                for (int p = 0; p < 8; ++p)
-                    bin[s2][p] = (__bf16)act_bf<ACT>(acc[s2 / 2][8 * (s2 % 2) + p], w0);
+            for (int s2 = 0; s2 < NS; ++s2) bin[s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
         }
         // ---------------- layers 2..L-1, two halves each
         for (int l = 2; l < m.L; ++l) {
@@ -961,19 +993,14 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
                 f32x16 acc[4];
                 half_gemm_w<0>(rs, bin, sb, h, acc, lane);
 #pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-                    for (int p = 0; p < 8; ++p)
-                        lo[s2][p] = (__bf16)act_bf<ACT>(acc[s2 / 2][8 * (s2 % 2) + p], w0);
+                for (int s2 = 0; s2 < 8; ++s2) lo[s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
             }
             {
                 f32x16 acc[4];
                 half_gemm_w<1>(rs, bin, sb, h, acc, lane);
 #pragma unroll
                 for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-                    for (int p = 0; p < 8; ++p)
-                        bin[8 + s2][p] = (__bf16)act_bf<ACT>(acc[s2 / 2][8 * (s2 % 2) + p], w0);
+                    bin[8 + s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
             }
 #pragma unroll
             for (int s2 = 0; s2 < 8; ++s2) bin[s2] = lo[s2];
@@ -992,7 +1019,8 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
                         fout = fmaf(sWout[32 * (4 * half + mt) + crow(r, h)],
-                                    act_bf<ACT>(acc[mt][r], w0), fout);
+                                    ACT == INRCT_FFN ? relu1(acc[mt][r]) : act_bf<ACT>(acc[mt][r], w0),
+                                    fout);
             }
         } else {
 #pragma unroll
