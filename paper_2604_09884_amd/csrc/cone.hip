@@ -207,7 +207,31 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
     // element offset of tap (iz, s, io): (iz + kPad) Np2 + (s + kPad) Np + io + kPad
     int srow = (lo + kPad) * Np + kPad * Np2 + kPad;
     float acc = 0.f;
-    for (int s = lo; s <= hi; ++s, Fo += c.dFo, Fz += dFz, srow += Np) {
+    // Four steps per iteration, all taps loaded before any is used, so each
+    // wave keeps sixteen gathers in flight; the sum stays in step order.
+    int s = lo;
+    for (; s + 3 <= hi; s += 4) {
+        float v[4][4], wo[4], wz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long long Foq = Fo + q * c.dFo, Fzq = Fz + q * dFz;
+            const int e = srow + q * Np + fx40_int(Fzq) * Np2 + fx40_int(Foq);
+            wo[q] = fx40_frac(Foq);
+            wz[q] = fx40_frac(Fzq);
+            v[q][0] = src[e];
+            v[q][1] = src[e + 1];
+            v[q][2] = src[e + Np2];
+            v[q][3] = src[e + Np2 + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc += (1.f - wz[q]) * ((1.f - wo[q]) * v[q][0] + wo[q] * v[q][1]) +
+                   wz[q] * ((1.f - wo[q]) * v[q][2] + wo[q] * v[q][3]);
+        Fo += 4 * c.dFo;
+        Fz += 4 * dFz;
+        srow += 4 * Np;
+    }
+    for (; s <= hi; ++s, Fo += c.dFo, Fz += dFz, srow += Np) {
         const int io = fx40_int(Fo), iz = fx40_int(Fz);
         const float wo = fx40_frac(Fo), wz = fx40_frac(Fz);
         const int e = srow + iz * Np2 + io;
@@ -230,19 +254,23 @@ __global__ __launch_bounds__(256) void k_cone_prescale(ConeDev g, const float *_
 }
 
 // Columns whose ray crosses the in-plane segment p1-p2 (central projection
-// of the end points, rounded outwards).
-__device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, double p1x,
-                                          double p1y, double p2x, double p2y, int *lo, int *hi) {
-    const double ax = vg.Sx - vg.Cx, ay = vg.Sy - vg.Cy;
-    const double D1x = p1x - vg.Sx, D1y = p1y - vg.Sy;
-    const double D2x = p2x - vg.Sx, D2y = p2y - vg.Sy;
-    const double u1 = (ax * D1y - ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
-    const double u2 = (ax * D2y - ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
-    const double c = 0.5 * (double)(g.Nu - 1);
-    const double a1 = u1 / g.du + c, a2 = u2 / g.du + c;
-    double l = floor(fmin(a1, a2)), r = ceil(fmax(a1, a2));
-    if (l < 0) l = 0;
-    if (r > g.Nu - 1) r = g.Nu - 1;
+// of the end points, rounded outwards).  Computed in single precision and
+// widened by a margin far above its rounding error: the caller tests every
+// candidate exactly, so extra columns cost time but never change a sum.
+__device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, float p1x,
+                                          float p1y, float p2x, float p2y, int *lo, int *hi) {
+    const float ax = (float)(vg.Sx - vg.Cx), ay = (float)(vg.Sy - vg.Cy);
+    const float sx = (float)vg.Sx, sy = (float)vg.Sy;
+    const float eux = (float)vg.eux, euy = (float)vg.euy;
+    const float D1x = p1x - sx, D1y = p1y - sy;
+    const float D2x = p2x - sx, D2y = p2y - sy;
+    const float u1 = (ax * D1y - ay * D1x) / (eux * D1y - euy * D1x);
+    const float u2 = (ax * D2y - ay * D2x) / (eux * D2y - euy * D2x);
+    const float c = 0.5f * (float)(g.Nu - 1);
+    const float a1 = u1 / (float)g.du + c, a2 = u2 / (float)g.du + c;
+    float l = floorf(fminf(a1, a2) - 0.01f), r = ceilf(fmaxf(a1, a2) + 0.01f);
+    l = fmaxf(l, 0.f);
+    r = fminf(r, (float)(g.Nu - 1));
     *lo = (int)l;
     *hi = (int)r;
 }
@@ -252,8 +280,8 @@ __device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, 
 template <int ZC>
 __device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__restrict__ rs,
                                             int ix, int iy, int z0, float (&acc)[ZC]) {
-    const double h = g.h;
-    const double x = -1.0 + (ix + 0.5) * h, y = -1.0 + (iy + 0.5) * h;
+    const float h = (float)g.h;
+    const float x = (float)(-1.0 + (ix + 0.5) * g.h), y = (float)(-1.0 + (iy + 0.5) * g.h);
     const int Nu = g.Nu, Nv = g.Nv;
     for (int j = 0; j < g.V; ++j) {
         const ConeView vg = g.view[j];
@@ -277,8 +305,9 @@ __device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__res
                 const long long E1 = c.Z1 + (long long)s * c.D1;  // > 0
                 // first row whose stencil reaches z0 - 1
                 const long long lo_t = (long long)(z0 - 1) << 40;
-                double bd = floor((double)(lo_t - E0) / (double)E1) - 1.0;
-                bd = bd < 0.0 ? 0.0 : (bd > (double)Nv ? (double)Nv : bd);
+                // row estimate in single precision; the walks below make it exact
+                float bd = floorf((float)(lo_t - E0) / (float)E1) - 1.f;
+                bd = bd < 0.f ? 0.f : (bd > (float)Nv ? (float)Nv : bd);
                 int b = (int)bd;
                 long long ph = E0 + (long long)b * E1;
                 while (b > 0 && ph - E1 >= lo_t) {
