@@ -1246,6 +1246,157 @@ __global__ void k_dw_reduce(const GemmTile *__restrict__ tiles, const float *__r
     grad[dst] = s;
 }
 
+// BF16 dW GEMMs with full-width tiles: a workgroup computes a 256 x 256
+// block of one layer's weight gradient (delta rows x input columns) over one
+// slice of points, so every delta and activation row of the slice is read
+// once per column block (layers of width 256 have one block).  The tile that
+// starts at column 0 also sums the delta rows (the bias gradient).  Four
+// waves, each a 128 x 128 quadrant (4 x 4 MFMA tiles); operands come straight
+// from global memory, two k-steps per group, double-buffered.
+struct GemmTile2 {
+    long long dlt_off;    // element offset of delta_l rows
+    long long act_off;    // element offset of a_{l-1} rows
+    long long theta_off;  // parameter offset of layer l (W then b)
+    int M, R, tn, bias;   // rows, inputs, first column, sums the bias gradient
+};
+constexpr int kDwPart = 256 * 256 + 256;  // partial floats per (tile, slice)
+
+__global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ tiles,
+                                                  const __bf16 *__restrict__ dlt,
+                                                  const __bf16 *__restrict__ act, long long P,
+                                                  long long ncols, int kslice, int accumulate,
+                                                  float *__restrict__ part, int ntiles) {
+    const GemmTile2 T = tiles[blockIdx.x];
+    const int ks = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, i = lane & 31;
+    const int wm = wave >> 1, wn = wave & 1;
+    const long long p0 = (long long)ks * kslice;
+    long long p1 = p0 + kslice;
+    if (p1 > ncols) p1 = ncols;
+    const __bf16 *ap[4], *bp[4];
+    bool aok[4], bok[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int row = wm * 128 + 32 * a + i;
+        aok[a] = row < T.M;
+        ap[a] = dlt + T.dlt_off + (long long)(aok[a] ? row : 0) * P + 8 * h;
+        const int col = T.tn + wn * 128 + 32 * a + i;
+        bok[a] = col < T.R;
+        bp[a] = act + T.act_off + (long long)(bok[a] ? col : 0) * P + 8 * h;
+    }
+    f32x16 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f32x16){0};
+    float bs[4] = {0.f, 0.f, 0.f, 0.f};
+    const bool dob = T.bias && wn == 0;
+    bf16x8 zero;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) zero[q] = (__bf16)0.f;
+    bf16x8 A[2][4][2], B[2][4][2];
+    // Rows and columns outside the layer read row 0 (always valid) and are
+    // zeroed after the load: no branch around a load, so the wait before a
+    // group's products counts only that group's loads.
+    auto load = [&](int buf, long long p) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                A[buf][a][j] = *(const bf16x8 *)(ap[a] + p + 16 * j);
+                B[buf][a][j] = *(const bf16x8 *)(bp[a] + p + 16 * j);
+            }
+    };
+    auto mask = [&](int buf) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!aok[a]) A[buf][a][j] = zero;
+                if (!bok[a]) B[buf][a][j] = zero;
+            }
+    };
+    auto compute = [&](int buf) {
+        mask(buf);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[buf][a][j], B[buf][b][j],
+                                                                        acc[a][b], 0, 0, 0);
+        if (dob) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bs[a] += (float)A[buf][a][j][q];
+        }
+    };
+    // the slice length is a multiple of 128 points: groups of 32 come in pairs
+    if (p0 < p1) load(0, p0);
+    for (long long p = p0; p < p1; p += 64) {
+        load(1, p + 32);
+        compute(0);
+        if (p + 64 < p1) load(0, p + 64);
+        compute(1);
+    }
+    float *__restrict__ out = part + ((long long)ks * ntiles + blockIdx.x) * kDwPart;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            // rows crow(r, h) = 8 (r / 4) + 4 h + r % 4 of the 32-row tile
+            float *o = out + (wm * 128 + 32 * a + 4 * h) * 256 + wn * 128 + 32 * b + i;
+            if (accumulate) {
+                // all sixteen earlier partials in flight before any store
+                float prev[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) prev[r] = o[(8 * (r / 4) + (r % 4)) * 256];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][b][r] += prev[r];
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) o[(8 * (r / 4) + (r % 4)) * 256] = acc[a][b][r];
+        }
+    if (dob) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const float t = bs[a] + __shfl_xor(bs[a], 32);
+            if (h == 0) {
+                float *o = out + 256 * 256 + wm * 128 + 32 * a + i;
+                *o = accumulate ? *o + t : t;
+            }
+        }
+    }
+}
+
+// grad[theta] = sum over slices (fixed order) of the full-width partials
+__global__ void k_dw_reduce2(const GemmTile2 *__restrict__ tiles, const float *__restrict__ part,
+                             int ntiles, int nks, float *__restrict__ grad) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)ntiles * kDwPart) return;
+    const int tile = (int)(t / kDwPart);
+    const int e = (int)(t % kDwPart);
+    const GemmTile2 T = tiles[tile];
+    long long dst;
+    if (e < 256 * 256) {
+        const int row = e / 256, col = T.tn + e % 256;
+        if (row >= T.M || col >= T.R) return;
+        dst = T.theta_off + (long long)row * T.R + col;
+    } else {
+        const int row = e - 256 * 256;
+        if (!T.bias || row >= T.M) return;
+        dst = T.theta_off + (long long)T.M * T.R + row;
+    }
+    float s = 0.f;
+    for (int k = 0; k < nks; ++k) s += part[((long long)k * ntiles + tile) * kDwPart + e];
+    grad[dst] = s;
+}
+
 }  // namespace inrct
 
 // ==================================================================== host
@@ -1422,9 +1573,15 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
                        dim3(256), 0, s, d, idx, k, j0, v, v_compact, scale, ncols, sink,
                        m->dlt.as<St>(), dlt_L1);
     INRCT_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_dw_gemm<BF>), dim3(m->ntiles, m->nks), dim3(256), 0, s,
-                       m->tiles.as<GemmTile>(), (const St *)m->dlt.ptr, (const St *)m->act.ptr,
-                       P, ncols, m->kslice, accumulate, m->part.as<float>(), m->ntiles);
+    if constexpr (BF)
+        hipLaunchKernelGGL(k_dw_gemm2, dim3(m->ntiles, m->nks), dim3(256), 0, s,
+                           m->tiles.as<GemmTile2>(), (const __bf16 *)m->dlt.ptr,
+                           (const __bf16 *)m->act.ptr, P, ncols, m->kslice, accumulate,
+                           m->part.as<float>(), m->ntiles);
+    else
+        hipLaunchKernelGGL((k_dw_gemm<BF>), dim3(m->ntiles, m->nks), dim3(256), 0, s,
+                           m->tiles.as<GemmTile>(), (const St *)m->dlt.ptr, (const St *)m->act.ptr,
+                           P, ncols, m->kslice, accumulate, m->part.as<float>(), m->ntiles);
     INRCT_CHECK_LAUNCH();
 }
 
@@ -1442,9 +1599,14 @@ void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t
         INRCT_DISPATCH_W_BF(m, launch_vjp_chunk, m, d, idx, k, j0, ncols, v, v_compact,
                             (float)scale, chunk > 0 ? 1 : 0, s);
     }
-    hipLaunchKernelGGL(k_dw_reduce, dim3((unsigned)cdiv((long long)m->ntiles * 16384, 256)),
-                       dim3(256), 0, s, m->tiles.as<GemmTile>(), m->part.as<float>(),
-                       m->ntiles, m->nks, grad);
+    if (m->bf16())
+        hipLaunchKernelGGL(k_dw_reduce2, dim3((unsigned)cdiv((long long)m->ntiles * kDwPart, 256)),
+                           dim3(256), 0, s, m->tiles.as<GemmTile2>(), m->part.as<float>(),
+                           m->ntiles, m->nks, grad);
+    else
+        hipLaunchKernelGGL(k_dw_reduce, dim3((unsigned)cdiv((long long)m->ntiles * 16384, 256)),
+                           dim3(256), 0, s, m->tiles.as<GemmTile>(), m->part.as<float>(),
+                           m->ntiles, m->nks, grad);
     INRCT_CHECK_LAUNCH();
 }
 
@@ -1580,6 +1742,27 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
                 m->sig_elems = (long long)L * W * P;
                 m->sig.alloc(m->sig_elems * sizeof(float));
             }
+            if (bf) {
+                // full-width dW tiles: layer l = 1..L+1, 256 input columns each
+                std::vector<GemmTile2> tiles2;
+                for (int l = 1; l <= L + 1; ++l) {
+                    GemmTile2 t{};
+                    t.M = l == L + 1 ? 1 : W;
+                    t.R = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
+                    t.dlt_off = (long long)(l - 1) * W * P;
+                    t.act_off = m->act_off[l - 1];
+                    t.theta_off = m->loff[l];
+                    for (int tn = 0; tn < t.R; tn += 256) {
+                        GemmTile2 u = t;
+                        u.tn = tn;
+                        u.bias = tn == 0;
+                        tiles2.push_back(u);
+                    }
+                }
+                m->ntiles = (int)tiles2.size();
+                upload(m->tiles, tiles2);
+                m->part.alloc((size_t)m->nks * m->ntiles * kDwPart * sizeof(float));
+            }
             // dW GEMM tiles: layer l = 1..L+1, delta rows M, inputs R (+ bias col)
             std::vector<GemmTile> tiles;
             for (int l = 1; l <= L + 1; ++l) {
@@ -1597,9 +1780,11 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
                         tiles.push_back(u);
                     }
             }
-            m->ntiles = (int)tiles.size();
-            upload(m->tiles, tiles);
-            m->part.alloc((size_t)m->nks * m->ntiles * 16384 * sizeof(float));
+            if (!bf) {
+                m->ntiles = (int)tiles.size();
+                upload(m->tiles, tiles);
+                m->part.alloc((size_t)m->nks * m->ntiles * 16384 * sizeof(float));
+            }
             // sampler scratch
             m->flags.alloc((size_t)m->n_fov);
             m->n_blk = cdiv(m->n_fov, 4096);
