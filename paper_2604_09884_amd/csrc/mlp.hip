@@ -739,11 +739,13 @@ __global__ __launch_bounds__(256) void k_eval_lds(MlpDev m, int n, int ntiles, i
 // each other's LDS, barrier and vector-unit time.  Biases initialise the
 // accumulators (from LDS), so no k-step carries them and no chunk is padded.
 constexpr int kRingWD = 3;                 // chunks in flight
-constexpr int kRingWNB = kRingWD + 1;      // ring slots
 constexpr int kChunkW = 32 * 1024;
 constexpr int kFovLdsN = 1024;             // largest grid side of the LDS path
 
+// D chunks in flight, D + 1 slots.
+template <int D>
 struct RingW {
+    static constexpr int NB = D + 1;
     char *ring;
     const char *gfrag;
     int slot, fill_slot, fill_src, nchunks, wave, lane;
@@ -755,22 +757,32 @@ struct RingW {
                   ring + dst_slot * kChunkW + f * 1024);
         }
     }
+    __device__ __forceinline__ void start(int n) {
+        nchunks = n;
+        slot = 0;
+        fill_slot = D % NB;
+        fill_src = D % n;
+#pragma unroll
+        for (int i = 0; i < D; ++i) issue(i % n, i);
+    }
     // Waits for the next chunk, then refills the slot every wave has finished
     // with (the barrier orders this wave's refill after the other waves'
     // reads of it and publishes the other waves' copies of the next chunk).
     __device__ __forceinline__ const bf16x8 *next() {
-        // all but this wave's copies of the next kRingWD - 1 chunks have landed
-        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+        // all but this wave's copies of the next D - 1 chunks have landed
+        static_assert(D == 2 || D == 3, "ring depth");
+        if constexpr (D == 3) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+        else asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
         __syncthreads();
         issue(fill_src, fill_slot);
         fill_src = fill_src + 1 == nchunks ? 0 : fill_src + 1;
-        fill_slot = fill_slot + 1 == kRingWNB ? 0 : fill_slot + 1;
+        fill_slot = fill_slot + 1 == NB ? 0 : fill_slot + 1;
         // read the ring through an address the compiler cannot trace, so no
         // read is hoisted above the wait and barrier (the copies are asm)
         unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring +
                        (unsigned)(slot * kChunkW);
         asm volatile("" : "+v"(off));
-        slot = slot + 1 == kRingWNB ? 0 : slot + 1;
+        slot = slot + 1 == NB ? 0 : slot + 1;
         return (const bf16x8 *)(__attribute__((address_space(3))) const bf16x8 *)(size_t)off;
     }
 };
@@ -840,11 +852,13 @@ __device__ __forceinline__ void layer1_w(const bf16x8 (&af)[8], const bf16x8 &b,
 // One hidden-layer half (four M-tiles) for one column tile: sixteen k-steps
 // in two chunks, fragments read one k-step ahead; the second chunk's
 // barrier comes before the first chunk's last products.
-template <int HALF>
-__device__ __forceinline__ void half_gemm_w(RingW &rs, const bf16x8 (&bin)[16], const float *sb,
+template <int HALF, bool BIAS, class Ring>
+__device__ __forceinline__ void half_gemm_w(Ring &rs, const bf16x8 (&bin)[16], const float *sb,
                                             int h, f32x16 (&acc)[4], int lane) {
+    // accumulators start at the bias (or at zero when there is none)
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = bias_tile(sb, 4 * HALF + mt, h);
+    for (int mt = 0; mt < 4; ++mt)
+        acc[mt] = BIAS ? bias_tile(sb, 4 * HALF + mt, h) : (f32x16){0};
     const bf16x8 *A = rs.next();
     bf16x8 cur[4], nxt[4];
     load_frags4(A, 0, lane, cur);
@@ -886,7 +900,7 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
                                                     const char *__restrict__ gfrag,
                                                     float *__restrict__ u) {
     constexpr int MT = 8, NS = 16;
-    __shared__ __attribute__((aligned(16))) char ring[kRingWNB * kChunkW];
+    __shared__ __attribute__((aligned(16))) char ring[(kRingWD + 1) * kChunkW];
     __shared__ float4 sB4[512];
     __shared__ __attribute__((aligned(16))) float sBias[kMaxDepth * 256];
     __shared__ float sWout[256];
@@ -912,9 +926,8 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
     const float b_out = m.b_out[0];
     const float w0 = m.omega0;
 
-    RingW rs{ring, gfrag, 0, kRingWD % kRingWNB, kRingWD % nchunks, nchunks, wave, lane};
-#pragma unroll
-    for (int i = 0; i < kRingWD; ++i) rs.issue(i % nchunks, i);
+    RingW<kRingWD> rs{ring, gfrag, 0, 0, 0, 0, wave, lane};
+    rs.start(nchunks);
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         float xc[3];
@@ -991,13 +1004,13 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
             bf16x8 lo[8];
             {
                 f32x16 acc[4];
-                half_gemm_w<0>(rs, bin, sb, h, acc, lane);
+                half_gemm_w<0, true>(rs, bin, sb, h, acc, lane);
 #pragma unroll
                 for (int s2 = 0; s2 < 8; ++s2) lo[s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
             }
             {
                 f32x16 acc[4];
-                half_gemm_w<1>(rs, bin, sb, h, acc, lane);
+                half_gemm_w<1, true>(rs, bin, sb, h, acc, lane);
 #pragma unroll
                 for (int s2 = 0; s2 < 8; ++s2)
                     bin[8 + s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
@@ -1012,8 +1025,8 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 f32x16 acc[4];
-                if (half == 0) half_gemm_w<0>(rs, bin, sb, h, acc, lane);
-                else half_gemm_w<1>(rs, bin, sb, h, acc, lane);
+                if (half == 0) half_gemm_w<0, true>(rs, bin, sb, h, acc, lane);
+                else half_gemm_w<1, true>(rs, bin, sb, h, acc, lane);
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -1034,6 +1047,251 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
         const float sacc = fout + __shfl_xor(fout, 32);
         if (lane < 32 && gidx >= 0) u[gidx] = sacc + b_out;
         // no drain: an older store in flight only makes the next ring wait stricter
+    }
+    // the copies of the chunks never consumed land before the wave ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// ------------------------------------------------------------------------
+// Width-256 BF16 VJP of the sampled points (FFN), Algorithm 1's
+// g = (n/|I|) sum_i v_i grad_theta f(x_i) before the dW contraction.  A
+// workgroup of eight waves (one 32-point column tile each) recomputes the
+// forward pass of k_eval_lds_w at 256 listed points, storing every layer
+// input a_0 .. a_L (BF16 rows of P points) and keeping the ReLU masks of
+// layers 1 .. L-1 in LDS, then runs the backward pass
+//   delta_L = c w_out . relu'(z_L),  delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),
+// storing delta_1 .. delta_L and delta_out = c, where c = scale v_i.  The
+// transposed weights follow the forward weights in one chunk stream through
+// a ring of three 32 KB slots.
+constexpr int kMaxDepthV = 6;
+struct VjpOut {
+    __bf16 *act;                      // a_0 .. a_L: act_off[l] + row * P + point
+    __bf16 *dlt;                      // delta_l at (l - 1) W P, delta_out at dlt_out
+    long long P;
+    long long act_off[kMaxDepth + 2];
+    long long dlt_out;
+};
+
+// Stores one operand's eight BF16 values of this lane's point.  Rows are
+// urow(p) + 4 h: the lane part 4 h P is folded into the (opaque) base and the
+// uniform parts urow(p) P stay scalar, so no per-store vector address is
+// precomputed.  P times any row fits in 32 bits.
+__device__ __forceinline__ void store_rows8(__bf16 *lane_base, const bf16x8 &v,
+                                            const int (&urow)[8], int P) {
+    unsigned long long b = (unsigned long long)lane_base;
+    asm volatile("" : "+v"(b));
+#pragma unroll
+    for (int p = 0; p < 8; ++p) ((__bf16 *)b)[urow[p] * P] = v[p];
+}
+
+// Uniform row parts of k-step s2 for the chained layers:
+// chain_feature(s2, h, p) = 16 s2 + 8 (p / 4) + p % 4 + 4 h.
+__device__ __forceinline__ void chain_urows(int s2, int (&row)[8]) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) row[p] = 16 * s2 + 8 * (p / 4) + (p % 4);
+}
+
+// delta = acc . mask (64 slots of one half), packed as BF16 operands.
+__device__ __forceinline__ void mask_pack(const f32x16 (&acc)[4], uint2 bits, int s2,
+                                          bf16x8 &out) {
+    const f32x16 &a = acc[s2 / 2];
+    const unsigned w = (s2 / 2) < 2 ? bits.x : bits.y;
+    const int sh = 16 * ((s2 / 2) & 1) + 8 * (s2 % 2);
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+        out[p] = (__bf16)((w >> (sh + p)) & 1u ? a[8 * (s2 % 2) + p] : 0.f);
+}
+
+__device__ __forceinline__ uint2 relu_bits4(const f32x16 (&acc)[4]) {
+    unsigned w[2] = {0u, 0u};
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) w[mt >> 1] |= (acc[mt][r] > 0.f ? 1u : 0u) << (16 * (mt & 1) + r);
+    return make_uint2(w[0], w[1]);
+}
+
+__global__ __launch_bounds__(512) void k_vjp_w(MlpDev m, const int32_t *__restrict__ idx,
+                                               long long k, long long j0,
+                                               const float *__restrict__ v, int v_compact,
+                                               float scale, int ntiles, int nchunks,
+                                               const char *__restrict__ gfrag, VjpOut o) {
+    constexpr int MT = 8, NS = 16;
+    __shared__ __attribute__((aligned(16))) char ring[3 * kChunkW];
+    __shared__ float4 sB4[512];
+    __shared__ __attribute__((aligned(16))) float sBias[kMaxDepthV * 256];
+    __shared__ float sWout[256];
+    // ReLU masks of layers 1 .. L-1: [wave][layer - 1][half][lane]
+    __shared__ uint2 sMask[8 * (kMaxDepthV - 1) * 2 * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+    for (int f = threadIdx.x; f < m.F; f += 512)
+        sB4[f] = make_float4(m.B[f * m.d], m.B[f * m.d + 1], m.d == 3 ? m.B[f * m.d + 2] : 0.f,
+                             0.f);
+    for (int i = threadIdx.x; i < m.L * 256; i += 512)
+        sBias[i] = m.theta[m.boff[1 + i / 256] + i % 256];
+    for (int i = threadIdx.x; i < 256; i += 512) sWout[i] = m.w_out[i];
+    __syncthreads();
+    const int P = (int)o.P;
+    const int L = m.L;
+    uint2 *msk = sMask + (size_t)wave * (kMaxDepthV - 1) * 2 * 64 + lane;
+
+    RingW<2> rs{ring, gfrag, 0, 0, 0, 0, wave, lane};
+    rs.start(nchunks);
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int pcol = tile * 256 + wave * 32 + (lane & 31);
+        const long long jg = j0 + pcol;
+        const bool ok = jg < k;
+        const long long jj = ok ? jg : k - 1;
+        const long long g = idx[jj];
+        float xc[3];
+        index_coords(m.fov, g, xc);
+        const float cot = ok ? scale * (v_compact ? v[jj] : v[g]) : 0.f;
+        // this lane's point, rows 4 h apart from the uniform row parts
+        __bf16 *actp = o.act + pcol + (long long)(4 * h) * P;
+        __bf16 *actp0 = actp + o.act_off[0];
+        bf16x8 bin[NS];
+        {
+            // ---------------- layer 1 (as k_eval_lds_w), storing the features
+            f32x16 acc[MT];
+            const int KS1 = m.F / 8;
+            const int nch1 = KS1 / 4;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = bias_tile(sBias, mt, h);
+            bf16x8 b, cur[MT], nxt[MT];
+            {
+                float4 q0[4];
+                ffn_rows(sB4, 0, h, q0);
+                ffn_feat1(q0, xc, b);
+            }
+            const bf16x8 *A = rs.next();
+            load_frags8(A, 0, lane, cur);
+            for (int c = 0; c < nch1; ++c) {
+                const bool more = c + 1 < nch1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int s = 4 * c + j;
+                    {
+                        int row[8];
+#pragma unroll
+                        for (int p = 0; p < 8; ++p) row[p] = 8 * s + p / 2 + ((p % 2) ? m.F : 0);
+                        store_rows8(actp0, b, row, P);
+                    }
+                    if (j < 3) {
+                        load_frags8(A, j + 1, lane, nxt);
+                    } else if (more) {
+                        A = rs.next();
+                        load_frags8(A, 0, lane, nxt);
+                    }
+                    float4 q[4];
+                    ffn_rows(sB4, min(s + 1, KS1 - 1), h, q);
+                    bf16x8 nb;
+                    __builtin_amdgcn_sched_barrier(0);
+                    layer1_w(cur, b, acc, q, xc, nb);
+                    b = nb;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) cur[mt] = nxt[mt];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            msk[0] = relu_bits4(*(const f32x16(*)[4]) & acc[0]);
+            msk[64] = relu_bits4(*(const f32x16(*)[4]) & acc[4]);
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                bin[s2] = act_pack8<INRCT_FFN>(acc[s2 / 2], 8 * (s2 % 2), 0.f);
+                int row[8];
+                chain_urows(s2, row);
+                store_rows8(actp + o.act_off[1], bin[s2], row, P);
+            }
+        }
+        // ---------------- layers 2..L-1, two halves each
+        for (int l = 2; l < L; ++l) {
+            const float *sb = sBias + (l - 1) * 256;
+            bf16x8 lo[8];
+            {
+                f32x16 acc[4];
+                half_gemm_w<0, true>(rs, bin, sb, h, acc, lane);
+                msk[(l - 1) * 128] = relu_bits4(acc);
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) lo[s2] = act_pack8<INRCT_FFN>(acc[s2 / 2], 8 * (s2 % 2), 0.f);
+            }
+            {
+                f32x16 acc[4];
+                half_gemm_w<1, true>(rs, bin, sb, h, acc, lane);
+                msk[(l - 1) * 128 + 64] = relu_bits4(acc);
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2)
+                    bin[8 + s2] = act_pack8<INRCT_FFN>(acc[s2 / 2], 8 * (s2 % 2), 0.f);
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 8; ++s2) bin[s2] = lo[s2];
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                int row[8];
+                chain_urows(s2, row);
+                store_rows8(actp + o.act_off[l], bin[s2], row, P);
+            }
+        }
+        // ---------------- last hidden layer: a_L stored, delta_L formed
+        bf16x8 dl[NS];
+        {
+            const float *sb = sBias + (L - 1) * 256;
+            __bf16 *dp = o.dlt + (long long)(L - 1) * 256 * P + pcol + (long long)(4 * h) * P;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                f32x16 acc[4];
+                if (half == 0) half_gemm_w<0, true>(rs, bin, sb, h, acc, lane);
+                else half_gemm_w<1, true>(rs, bin, sb, h, acc, lane);
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) {
+                    const int sg = 8 * half + s2;
+                    int row[8];
+                    chain_urows(sg, row);
+                    const bf16x8 a = act_pack8<INRCT_FFN>(acc[s2 / 2], 8 * (s2 % 2), 0.f);
+                    store_rows8(actp + o.act_off[L], a, row, P);
+                    bf16x8 d;
+#pragma unroll
+                    for (int p = 0; p < 8; ++p) {
+                        const float z = acc[s2 / 2][8 * (s2 % 2) + p];
+                        d[p] = (__bf16)(z > 0.f ? cot * sWout[row[p] + 4 * h] : 0.f);
+                    }
+                    dl[sg] = d;
+                    store_rows8(dp, d, row, P);
+                }
+            }
+        }
+        if (h == 0) o.dlt[o.dlt_out + pcol] = (__bf16)cot;
+        // ---------------- backward: delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1})
+        for (int l = L; l >= 2; --l) {
+            __bf16 *dp = o.dlt + (long long)(l - 2) * 256 * P + pcol + (long long)(4 * h) * P;
+            bf16x8 nlo[8];
+            {
+                f32x16 acc[4];
+                half_gemm_w<0, false>(rs, dl, nullptr, h, acc, lane);
+                const uint2 bits = msk[(l - 2) * 128];
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) {
+                    mask_pack(acc, bits, s2, nlo[s2]);
+                    int row[8];
+                    chain_urows(s2, row);
+                    store_rows8(dp, nlo[s2], row, P);
+                }
+            }
+            {
+                f32x16 acc[4];
+                half_gemm_w<1, false>(rs, dl, nullptr, h, acc, lane);
+                const uint2 bits = msk[(l - 2) * 128 + 64];
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) {
+                    mask_pack(acc, bits, s2, dl[8 + s2]);
+                    int row[8];
+                    chain_urows(8 + s2, row);
+                    store_rows8(dp, dl[8 + s2], row, P);
+                }
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 8; ++s2) dl[s2] = nlo[s2];
+        }
     }
     // the copies of the chunks never consumed land before the wave ends
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1444,6 +1702,14 @@ void model_pack(inrct_model *m, const float *theta, hipStream_t s) {
                        m->d_loff.as<long long>(), m->pk_layer.as<int>(), m->pk_mt.as<int>(),
                        m->pk_s.as<int>());
     INRCT_CHECK_LAUNCH();
+    if (m->vjp_lds) {
+        const long long tv = (m->nfrag_h + m->nfrag_vb) * 64 * 8;
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)cdiv(tv, 256)), dim3(256), 0, s, d, theta, 1,
+                           m->frag_v.ptr, (char *)m->frag_v.ptr + m->nfrag_h * 64 * 16,
+                           m->nfrag_h, m->nfrag_vb, m->d_loff.as<long long>(),
+                           m->pkv_layer.as<int>(), m->pkv_mt.as<int>(), m->pkv_s.as<int>());
+        INRCT_CHECK_LAUNCH();
+    }
     if (m->nfrag_h > 0) {
         const long long th = m->nfrag_h * 64 * 8;
         hipLaunchKernelGGL(k_pack, dim3((unsigned)cdiv(th, 256)), dim3(256), 0, s, d, theta, 1,
@@ -1568,10 +1834,24 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
     }
     const long long P = m->P_alloc;
     const long long dlt_L1 = (long long)m->arch.depth * m->arch.width * P;
-    const long long per_block = 4LL * 32 * NT;
-    hipLaunchKernelGGL((k_vjp_tile<W, NT, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
-                       dim3(256), 0, s, d, idx, k, j0, v, v_compact, scale, ncols, sink,
-                       m->dlt.as<St>(), dlt_L1);
+    if (BF && W == 256 && ACT == INRCT_FFN && m->vjp_lds) {
+        VjpOut o{};
+        o.act = m->act.as<__bf16>();
+        o.dlt = m->dlt.as<__bf16>();
+        o.P = P;
+        for (int l = 0; l < kMaxDepth + 2; ++l) o.act_off[l] = m->act_off[l];
+        o.dlt_out = dlt_L1;
+        const int ntiles = (int)cdiv(ncols, 256);
+        const int grid = (int)std::min<long long>(ntiles, m->n_cu);
+        const int nchunks = (int)((m->nfrag_h + m->nfrag_vb) / 32);
+        hipLaunchKernelGGL(k_vjp_w, dim3((unsigned)grid), dim3(512), 0, s, d, idx, k, j0, v,
+                           v_compact, scale, ntiles, nchunks, (const char *)m->frag_v.ptr, o);
+    } else {
+        const long long per_block = 4LL * 32 * NT;
+        hipLaunchKernelGGL((k_vjp_tile<W, NT, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
+                           dim3(256), 0, s, d, idx, k, j0, v, v_compact, scale, ncols, sink,
+                           m->dlt.as<St>(), dlt_L1);
+    }
     INRCT_CHECK_LAUNCH();
     if constexpr (BF)
         hipLaunchKernelGGL(k_dw_gemm2, dim3(m->ntiles, m->nks), dim3(256), 0, s,
@@ -1594,7 +1874,7 @@ void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t
     int chunk = 0;
     for (long long j0 = 0; j0 < k; j0 += P, ++chunk) {
         long long ncols = k - j0 < P ? k - j0 : P;
-        ncols = cdiv(ncols, 128) * 128;
+        ncols = cdiv(ncols, 256) * 256;  // P is a multiple of 256
         if (ncols > P) ncols = P;
         INRCT_DISPATCH_W_BF(m, launch_vjp_chunk, m, d, idx, k, j0, ncols, v, v_compact,
                             (float)scale, chunk > 0 ? 1 : 0, s);
@@ -1716,6 +1996,26 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
                 upload(m->pkh_mt, hm);
                 upload(m->pkh_s, hs);
                 m->frag_h.alloc(m->nfrag_h * 64 * 16);
+                m->vjp_lds = a.kind == INRCT_FFN && a.n_freq % 32 == 0 &&
+                             a.n_freq <= 512 && L >= 2 && L <= kMaxDepthV;
+                if (m->vjp_lds) {
+                    // backward stream: layers L .. 2, by half, k-step x 4 M-tiles
+                    // of W_l^T (M-tiles over the inputs of layer l)
+                    std::vector<int> vl = hl, vm = hm, vs = hs;
+                    for (int l = L; l >= 2; --l)
+                        for (int half = 0; half < 2; ++half)
+                            for (int s = 0; s < 16; ++s)
+                                for (int mt = 0; mt < 4; ++mt) {
+                                    vl.push_back(l);
+                                    vm.push_back(half * 4 + mt);
+                                    vs.push_back(s);
+                                }
+                    m->nfrag_vb = (long long)vl.size() - m->nfrag_h;
+                    upload(m->pkv_layer, vl);
+                    upload(m->pkv_mt, vm);
+                    upload(m->pkv_s, vs);
+                    m->frag_v.alloc((m->nfrag_h + m->nfrag_vb) * 64 * 16);
+                }
             }
             upload(m->pk_layer, fl);
             upload(m->pk_mt, fm);
@@ -1724,7 +2024,7 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             m->frag.alloc(std::max<long long>(1, m->nfrag) * 64 * fbytes);
             m->fragT.alloc(std::max<long long>(1, m->nfragT) * 64 * fbytes);
             // VJP scratch: chunk of P_alloc points
-            const long long kpad = cdiv(m->max_k, 128) * 128;
+            const long long kpad = cdiv(m->max_k, 256) * 256;
             m->P_alloc = std::min<long long>(kpad, 65536);
             m->nks = (int)cdiv(m->P_alloc, m->kslice);
             const long long P = m->P_alloc;

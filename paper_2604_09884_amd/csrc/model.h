@@ -22,6 +22,11 @@ struct inrct_model {
     // chunk stream of the width-256 BF16 grid-evaluation kernel
     long long nfrag_h = 0;
     inrct::DevBuf frag_h, pkh_layer, pkh_mt, pkh_s;
+    // chunk stream of the width-256 VJP kernel: the forward stream (nfrag_h
+    // fragments, as frag_h) followed by nfrag_vb transposed fragments
+    long long nfrag_vb = 0;
+    inrct::DevBuf frag_v, pkv_layer, pkv_mt, pkv_s;
+    bool vjp_lds = false;
 
     // VJP chunk scratch
     long long P_alloc = 0;       // points per chunk (row stride)
