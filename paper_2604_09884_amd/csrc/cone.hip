@@ -318,23 +318,27 @@ __device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__res
                     ++b;
                     ph += E1;
                 }
-                const float *rc = rj + a;
+                // One pass over the rows from b on: a row whose stencil
+                // starts at voxel i0 gives (1 - w) to i0 and w to i0 + 1.
+                // Every voxel still receives its terms in increasing row
+                // order with the same products, so the sums are unchanged.
+                const float *rp = rj + a + (size_t)b * Nu;
+                while (b < Nv && fx40_int(ph) == z0 - 1) {
+                    acc[0] += wo * fx40_frac(ph) * rp[0];
+                    ++b;
+                    ph += E1;
+                    rp += Nu;
+                }
 #pragma unroll
                 for (int jz = 0; jz < ZC; ++jz) {
-                    const int iz = z0 + jz;
-                    int bb = b;
-                    long long pp = ph;
-                    while (bb < Nv) {
-                        const int i0 = fx40_int(pp);
-                        if (i0 > iz) break;
-                        const float w = fx40_frac(pp);
-                        acc[jz] += wo * (i0 == iz ? 1.f - w : w) * rc[(size_t)bb * Nu];
-                        ++bb;
-                        pp += E1;
-                    }
-                    while (b < Nv && fx40_int(ph) < iz) {
+                    while (b < Nv && fx40_int(ph) == z0 + jz) {
+                        const float w = fx40_frac(ph);
+                        const float r = rp[0];
+                        acc[jz] += wo * (1.f - w) * r;
+                        if (jz + 1 < ZC) acc[jz + 1] += wo * w * r;
                         ++b;
                         ph += E1;
+                        rp += Nu;
                     }
                 }
             }
