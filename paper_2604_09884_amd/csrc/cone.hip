@@ -9,7 +9,8 @@
 // exactly the interpolation weights P applies, and neither does float64
 // work per sample.
 //
-// P: one ray per lane, 64 columns x 4 rows per workgroup, slices visited in
+// P: one ray per lane, a wave an 8 x 8 patch of (column, row) rays and a
+// workgroup 16 x 16, slices visited in
 // order.  Rays whose principal axis is x read a transposed copy of the
 // volume ([z][x][y]) so that neighbouring lanes read neighbouring addresses
 // in both cases.
@@ -188,8 +189,10 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
                                                   float *__restrict__ z, int ncx, int ncy) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb < 0) return;
-    const int a = (lb % ncx) * 64 + (threadIdx.x & 63);
-    const int b = ((lb / ncx) % ncy) * 4 + (threadIdx.x >> 6);
+    // a wave is an 8 x 8 patch of rays (columns x rows); a block 16 x 16
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int a = (lb % ncx) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int b = ((lb / ncx) % ncy) * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int j = lb / (ncx * ncy);
     if (a >= g.Nu || b >= g.Nv) return;
     const ConeCol c = g.col[(size_t)j * g.Nu + a];
@@ -352,8 +355,10 @@ __global__ __launch_bounds__(256) void k_cone_bp(ConeDev g, const float *__restr
                                                  float *__restrict__ v, int nbx, int nby) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb < 0) return;
-    const int ix = (lb % nbx) * 64 + (threadIdx.x & 63);
-    const int iy = ((lb / nbx) % nby) * 4 + (threadIdx.x >> 6);
+    // a wave is an 8 x 8 patch of (x, y) voxel columns; a block 16 x 16
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ix = (lb % nbx) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int iy = ((lb / nbx) % nby) * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int z0 = (lb / (nbx * nby)) * kZc;
     if (ix >= g.N || iy >= g.N) return;
     float acc[kZc];
@@ -387,7 +392,7 @@ void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
     hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)cdiv(d.N, 32), (unsigned)cdiv(d.N, 32), d.N),
                        dim3(256), 0, s, u, up, hd->any_x ? utp : nullptr, d.N);
     INRCT_CHECK_LAUNCH();
-    const int ncx = (int)cdiv(d.Nu, 64), ncy = (int)cdiv(d.Nv, 4);
+    const int ncx = (int)cdiv(d.Nu, 16), ncy = (int)cdiv(d.Nv, 16);
     hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ncy * d.V)), dim3(256), 0, s, d, up, utp, z,
                        ncx, ncy);
     INRCT_CHECK_LAUNCH();
@@ -405,7 +410,7 @@ static const float *cone_prescale(inrct_geom *hd, const float *r, hipStream_t s)
 void cone_backproject(inrct_geom *hd, const float *r, float *v, hipStream_t s) {
     const float *rs = cone_prescale(hd, r, s);
     const ConeDev d = hd->cone();
-    const int nbx = (int)cdiv(d.N, 64), nby = (int)cdiv(d.N, 4), nbz = (int)cdiv(d.N, kZc);
+    const int nbx = (int)cdiv(d.N, 16), nby = (int)cdiv(d.N, 16), nbz = (int)cdiv(d.N, kZc);
     hipLaunchKernelGGL(k_cone_bp, dim3((unsigned)(nbx * nby * nbz)), dim3(256), 0, s, d, rs, v,
                        nbx, nby);
     INRCT_CHECK_LAUNCH();

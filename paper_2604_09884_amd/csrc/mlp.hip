@@ -852,9 +852,16 @@ __device__ __forceinline__ void layer1_w(const bf16x8 (&af)[8], const bf16x8 &b,
 // One hidden-layer half (four M-tiles) for one column tile: sixteen k-steps
 // in two chunks, fragments read one k-step ahead; the second chunk's
 // barrier comes before the first chunk's last products.
-template <int HALF, bool BIAS, class Ring>
+struct NoSide {
+    __device__ __forceinline__ void operator()(int) const {}
+};
+
+// side(s) runs after the products of k-step s are issued: vector work of an
+// earlier half (conversions, the output layer) overlaps the matrix core.
+template <int HALF, bool BIAS, class Ring, class Side = NoSide>
 __device__ __forceinline__ void half_gemm_w(Ring &rs, const bf16x8 (&bin)[16], const float *sb,
-                                            int h, f32x16 (&acc)[4], int lane) {
+                                            int h, f32x16 (&acc)[4], int lane,
+                                            Side &&side = Side()) {
     // accumulators start at the bias (or at zero when there is none)
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -872,6 +879,7 @@ __device__ __forceinline__ void half_gemm_w(Ring &rs, const bf16x8 (&bin)[16], c
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
             acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[mt], bin[s], acc[mt], 0, 0, 0);
+        side(s);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) cur[mt] = nxt[mt];
@@ -1002,19 +1010,15 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
         for (int l = 2; l < m.L; ++l) {
             const float *sb = sBias + (l - 1) * 256;
             bf16x8 lo[8];
-            {
-                f32x16 acc[4];
-                half_gemm_w<0, true>(rs, bin, sb, h, acc, lane);
+            f32x16 acc0[4], acc1[4];
+            half_gemm_w<0, true>(rs, bin, sb, h, acc0, lane);
+            // half 0's outputs are converted between half 1's products
+            half_gemm_w<1, true>(rs, bin, sb, h, acc1, lane, [&](int s) {
+                if (s < 8) lo[s] = act_pack8<ACT>(acc0[s / 2], 8 * (s % 2), w0);
+            });
 #pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2) lo[s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
-            }
-            {
-                f32x16 acc[4];
-                half_gemm_w<1, true>(rs, bin, sb, h, acc, lane);
-#pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2)
-                    bin[8 + s2] = act_pack8<ACT>(acc[s2 / 2], 8 * (s2 % 2), w0);
-            }
+            for (int s2 = 0; s2 < 8; ++s2)
+                bin[8 + s2] = act_pack8<ACT>(acc1[s2 / 2], 8 * (s2 % 2), w0);
 #pragma unroll
             for (int s2 = 0; s2 < 8; ++s2) bin[s2] = lo[s2];
         }
@@ -1022,19 +1026,23 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
         float fout = 0.f;
         if (m.L >= 2) {
             const float *sb = sBias + (m.L - 1) * 256;
+            f32x16 acc0[4], acc1[4];
+            auto out4 = [&](const f32x16 (&acc)[4], int half, int s) {
+                // four of the half's 64 outputs: M-tile s / 4, slots 4 (s % 4) ..
+                const int mt = s / 4;
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                f32x16 acc[4];
-                if (half == 0) half_gemm_w<0, true>(rs, bin, sb, h, acc, lane);
-                else half_gemm_w<1, true>(rs, bin, sb, h, acc, lane);
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 4 * (s % 4) + i;
+                    fout = fmaf(sWout[32 * (4 * half + mt) + crow(r, h)],
+                                ACT == INRCT_FFN ? relu1(acc[mt][r]) : act_bf<ACT>(acc[mt][r], w0),
+                                fout);
+                }
+            };
+            half_gemm_w<0, true>(rs, bin, sb, h, acc0, lane);
+            // half 0's output-layer terms between half 1's products
+            half_gemm_w<1, true>(rs, bin, sb, h, acc1, lane, [&](int s) { out4(acc0, 0, s); });
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        fout = fmaf(sWout[32 * (4 * half + mt) + crow(r, h)],
-                                    ACT == INRCT_FFN ? relu1(acc[mt][r]) : act_bf<ACT>(acc[mt][r], w0),
-                                    fout);
-            }
+            for (int s = 0; s < 16; ++s) out4(acc1, 1, s);
         } else {
 #pragma unroll
             for (int s2 = 0; s2 < NS; ++s2)
