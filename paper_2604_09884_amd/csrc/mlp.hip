@@ -2033,7 +2033,7 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             m->fragT.alloc(std::max<long long>(1, m->nfragT) * 64 * fbytes);
             // VJP scratch: chunk of P_alloc points
             const long long kpad = cdiv(m->max_k, 256) * 256;
-            m->P_alloc = std::min<long long>(kpad, 65536);
+            m->P_alloc = std::min<long long>(kpad, 262144);
             m->nks = (int)cdiv(m->P_alloc, m->kslice);
             const long long P = m->P_alloc;
             const int K1 = layer_K(a.kind, a.n_freq, d, W, 1);

@@ -80,7 +80,7 @@ def reservation_bytes(p: Problem, mlp_dtype: Optional[str] = None) -> int:
     params = p.arch.n_params
     opt = 4 * params * 6                                                  # theta, m, v, g, packs
     k = p.k(p.n_fov())
-    P = min(65536, -(-k // 256) * 256)
+    P = min(262144, -(-k // 256) * 256)
     W, L = p.arch.width, p.arch.depth
     k1 = p.arch.enc_dim
     es = 2 if dtype == "bf16" else 4
