@@ -749,15 +749,25 @@ struct RingW {
     char *ring;
     const char *gfrag;
     int slot, fill_slot, fill_src, nchunks, wave, lane;
+    unsigned lds0;          // LDS byte address of the ring (uniform)
+    const char *gsrc;       // this lane's 16 bytes of this wave's first fragment
     __device__ __forceinline__ void issue(int src, int dst_slot) {
+        // the LDS destination is uniform: computed once per copy in scalar
+        // registers, no per-copy address-space conversion
+        const unsigned m0 = lds0 + (unsigned)(dst_slot * kChunkW + wave * 4 * 1024);
+        const char *g = gsrc + (size_t)src * 32 * 1024;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = wave * 4 + i;
-            dma16(gfrag + ((size_t)src * 32 + f) * 1024 + lane * 16,
-                  ring + dst_slot * kChunkW + f * 1024);
-        }
+        for (int i = 0; i < 4; ++i)
+            asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                         :
+                         : "s"(m0 + i * 1024), "v"(g + i * 1024)
+                         : "memory", "m0");
     }
     __device__ __forceinline__ void start(int n) {
+        wave = __builtin_amdgcn_readfirstlane(wave);
+        lds0 = __builtin_amdgcn_readfirstlane(
+            (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring);
+        gsrc = gfrag + (size_t)wave * 4 * 1024 + lane * 16;
         nchunks = n;
         slot = 0;
         fill_slot = D % NB;
@@ -934,7 +944,7 @@ __global__ __launch_bounds__(512) void k_eval_lds_w(MlpDev m, int n, int ntiles,
     const float b_out = m.b_out[0];
     const float w0 = m.omega0;
 
-    RingW<kRingWD> rs{ring, gfrag, 0, 0, 0, 0, wave, lane};
+    RingW<kRingWD> rs{ring, gfrag, 0, 0, 0, 0, wave, lane, 0u, nullptr};
     rs.start(nchunks);
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -1143,7 +1153,7 @@ __global__ __launch_bounds__(512) void k_vjp_w(MlpDev m, const int32_t *__restri
     const int L = m.L;
     uint2 *msk = sMask + (size_t)wave * (kMaxDepthV - 1) * 2 * 64 + lane;
 
-    RingW<2> rs{ring, gfrag, 0, 0, 0, 0, wave, lane};
+    RingW<2> rs{ring, gfrag, 0, 0, 0, 0, wave, lane, 0u, nullptr};
     rs.start(nchunks);
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
