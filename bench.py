@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--mlp-dtype", default=None, choices=[None, "bf16", "fp32"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve", type=int, default=0, metavar="R",
+                    help="measure serving instead: R requests of the C5 mix stepped together "
+                         "versus one at a time (prints its own JSON line)")
+    ap.add_argument("--serve-steps", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy before the steps (a "
                          "reference for hardware byte counters)")
@@ -149,12 +153,68 @@ def e_kernel_traffic():
     return int(m_b.group(1))
 
 
+def serve_bench(a):
+    """C5: R requests of the serving mix, each run alone and then all
+    together; throughput over all requests' steps, tick latencies, and a
+    check that every request ends with the parameters it had alone."""
+    import torch
+
+    from paper_2604_09884_amd import configs, synth
+    from paper_2604_09884_amd.serve import DONE, Request, Server
+
+    torch.cuda.set_device(0)
+    probs = configs.serving_mix(a.serve, steps=a.serve_steps)
+    t0 = time.time()
+    reqs = [Request(problem=p, y=synth.sinogram(p).astype(np.float32), steps=p.steps)
+            for p in probs]
+    log("C5 mix: %s; sinograms in %.1f s" % ([p.name for p in probs], time.time() - t0))
+    # warm-up: one request of each architecture kind, one step
+    for r in reqs[:2]:
+        srv = Server(n_streams=1)
+        srv.submit(Request(problem=r.problem, y=r.y, steps=1))
+        srv.run()
+    torch.cuda.synchronize()
+    alone, t_seq = [], 0.0
+    for r in reqs:
+        srv = Server(n_streams=1)
+        rid = srv.submit(r)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        srv.run()
+        t_seq += time.perf_counter() - t
+        assert srv.status(rid).state == DONE, srv.status(rid).error
+        alone.append(srv.status(rid).theta)
+    srv = Server(n_streams=4)
+    ids = [srv.submit(r) for r in reqs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    srv.run()
+    t_mix = time.perf_counter() - t
+    same = all(srv.status(i).state == DONE and np.array_equal(srv.status(i).theta, th)
+               for i, th in zip(ids, alone))
+    m = srv.metrics()
+    steps = sum(r.steps for r in reqs)
+    out = {
+        "metric": "served grad steps/s (C5 serving mix)", "value": steps / t_mix,
+        "unit": "steps/s", "n_gpus": 1, "requests": len(reqs), "steps_per_request": a.serve_steps,
+        "sequential_steps_per_s": steps / t_seq, "speedup_vs_sequential": t_seq / t_mix,
+        "tick_ms_p50": m["tick_ms_p50"], "tick_ms_p99": m["tick_ms_p99"],
+        "mix_equals_alone": bool(same), "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": "C5 serving mix (seed 5005)",
+                   "requests": [p.name + ":" + p.arch.kind + ":" + p.mlp_dtype for p in probs]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % a.gpus, flush=True)
         sys.exit(2)
+    if a.serve:
+        serve_bench(a)
+        return
     import torch
 
     from paper_2604_09884_amd import configs, lib as L, ops, synth

@@ -190,6 +190,44 @@ C4 = Problem(
 CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4}
 
 
+# C5, the serving mix: request kinds uniform over {2D-256, 2D-512, 3D-128,
+# 3D-256}; 2D parallel beam with 60 or 90 views over 180 deg and ceil(N
+# sqrt 2) bins rounded up to odd; 3D cone beam with 20, 40 or 60 views over
+# 360 deg and a 2N x 2N detector on the shared world geometry; architecture
+# uniform over {C1's FFN (full sampling, lr 1e-3), C2's SIREN (n/16, lr
+# 1e-4)} with the request's input dimension; arrivals drawn from seed 5005.
+def serving_mix(n_requests: int, seed: int = 5005, steps: int = 4):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_requests):
+        kind = ("2d-256", "2d-512", "3d-128", "3d-256")[rng.integers(4)]
+        ffn = bool(rng.integers(2))
+        N = int(kind.split("-")[1])
+        dim = 2 if kind.startswith("2d") else 3
+        if ffn:
+            arch = _ffn(dim, 64, 128, 3)
+            extra = dict(k_frac=1.0, lr=1e-3, mlp_dtype="fp32")
+        else:
+            arch = _siren(dim, 256, 5)
+            extra = dict(k_frac=1.0 / 16, lr=1e-4, mlp_dtype="bf16")
+        seeds = dict(seed_phantom=6000 + i, seed_noise=7000 + i, seed_init=8000 + i,
+                     seed_sampler=9000 + i, steps=steps, n_ellipses=10, photons=0.0)
+        if dim == 2:
+            views = int((60, 90)[rng.integers(2)])
+            bins = int(math.ceil(N * math.sqrt(2)))
+            bins += 1 - bins % 2
+            p = par2d_problem(N, views, bins, arch=arch, name=f"mix{i}-{kind}-{views}v",
+                              **extra, **seeds)
+        else:
+            views = int((20, 40, 60)[rng.integers(3)])
+            p = cone_problem(N, views, 2 * N, arch=arch, name=f"mix{i}-{kind}-{views}v",
+                             n_ellipses=20, **{k: v for k, v in extra.items()},
+                             **{k: v for k, v in seeds.items() if k != "n_ellipses"})
+        out.append(p)
+    return out
+
+
 def cone_problem(N: int, n_views: int, det: int, **kw) -> Problem:
     """A cone-beam problem on the shared world geometry (detector det x det)."""
     base = dict(name=f"cone3d-{N}", dim=3, N=N, geometry="cone3d",
