@@ -84,23 +84,27 @@ def cpu_baseline(p, target_s):
 
     # E: oracle forward on S points (grow S until ~budget)
     S = 2048
+    nz = p.N if p.dim == 3 else 1
     while True:
-        pts = fov2[rng.choice(fov2.size, size=S)] + rng.integers(0, p.N, S) * p.N * p.N
-        X = ogrid.coords(3, p.N, pts)
+        pts = fov2[rng.choice(fov2.size, size=S)] + rng.integers(0, nz, S) * p.N * p.N
+        X = ogrid.coords(p.dim, p.N, pts)
         t_e = timed(lambda: oinr.forward(theta, B, X, p.arch))
         if t_e > budget / 2 or S >= 1 << 18:
             break
         S *= 2
     per_E = t_e / S * n
     # P and P^T on R rays of view 0
-    R = 1024
-    p0, d = ogeo.cone3d_rays(p.n_views, p.n_u, p.n_v, p.du, p.dv, p.dso, p.dod,
-                             views=[0], rows=np.arange(p.n_v // 2 - 1, p.n_v // 2 + 1))
+    if p.dim == 3:
+        p0, d = ogeo.cone3d_rays(p.n_views, p.n_u, p.n_v, p.du, p.dv, p.dso, p.dod,
+                                 views=[0], rows=np.arange(p.n_v // 2 - 1, p.n_v // 2 + 1))
+    else:
+        p0, d = ogeo.problem_rays(p, views=[0])
+    R = min(1024, p0.shape[0])
     sel = rng.choice(p0.shape[0], size=R, replace=False)
     t0 = time.perf_counter()
-    A = joseph.system_matrix(p.N, 3, p0[sel], d[sel])
+    A = joseph.system_matrix(p.N, p.dim, p0[sel], d[sel])
     t_build = time.perf_counter() - t0
-    vol = np.ones(p.N ** 3)
+    vol = np.ones(p.N ** p.dim)
     t_p = t_build + timed(lambda: A @ vol)
     r = rng.standard_normal(R)
     t_pt = t_build + timed(lambda: A.T @ r)
@@ -109,7 +113,8 @@ def cpu_baseline(p, target_s):
     per_PT = t_pt / R * m
     # VJP on Q sampled points
     Q = 1024
-    Xq = ogrid.coords(3, p.N, fov2[rng.choice(fov2.size, size=Q)] + (p.N // 2) * p.N * p.N)
+    Xq = ogrid.coords(p.dim, p.N, fov2[rng.choice(fov2.size, size=Q)]
+                      + (nz // 2) * p.N * p.N)
     t_v = timed(lambda: oinr.vjp(theta, B, Xq, rng.standard_normal(Q), p.arch))
     per_V = t_v / Q * k
     # sampler on D draws
@@ -277,7 +282,8 @@ def main():
                             % (flop_per_point, model.n_fov),
                 "avg_launch_ms": e_ms}
     out = {
-        "metric": "grad steps/s at 501^3 cone-beam 20 views",
+        "metric": ("grad steps/s at 501^3 cone-beam 20 views" if a.config == "c4"
+                   else "grad steps/s at " + p.name),
         "value": 1e3 / ms_step,
         "unit": "steps/s",
         "n_gpus": 1,
@@ -288,7 +294,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
-        "data": "synthetic (seeded ellipsoid phantom, closed-form chord data, Poisson 1e5)",
+        "data": "synthetic (seeded %s phantom, closed-form chord data, %s)"
+                % ("ellipsoid" if p.dim == 3 else "ellipse",
+                   "Poisson %.0e" % p.photons if p.photons else "noiseless"),
         "config": {"workload": p.name, "grid": "%d^%d" % (p.N, p.dim),
                    "views": p.n_views, "detector": "%dx%d" % (p.n_v, p.n_u),
                    "n_fov": model.n_fov, "k": k, "params": model.n_params,
@@ -298,7 +306,7 @@ def main():
         "loss_last": loss,
         "roofline": roofline,
     }
-    if not a.no_cpu and a.config in ("c1", "c2", "c3", "c4") and p.dim == 3:
+    if not a.no_cpu:
         log("timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
     print(json.dumps(out), flush=True)

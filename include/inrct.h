@@ -65,6 +65,7 @@ extern "C" {
 /* geometry kinds */
 #define INRCT_PAR2D 1       /* 2D parallel beam                            */
 #define INRCT_CONE3D 2      /* 3D circular cone beam, flat detector        */
+#define INRCT_FAN2D 3       /* 2D fan beam, flat detector (Sec. IV-A)      */
 
 /* INR kinds and MLP precision */
 #define INRCT_FFN 1         /* Fourier features + ReLU MLP                 */
@@ -90,12 +91,16 @@ typedef struct {
  *        (k - (n_u-1)/2) du; n_v must be 1.
  * CONE3D: source sid (cos, sin, 0), detector centre -idd (cos, sin, 0),
  *        detector axes (-sin, cos, 0) and (0, 0, 1); pixel (a, b) at
- *        ((a - (n_u-1)/2) du, (b - (n_v-1)/2) dv). */
+ *        ((a - (n_u-1)/2) du, (b - (n_v-1)/2) dv).
+ * FAN2D: the in-plane part of CONE3D: source sid (cos, sin), detector
+ *        centre -idd (cos, sin), detector axis (-sin, cos), bin a at
+ *        (a - (n_u-1)/2) du; n_v must be 1 and sid > 1.4143 (1 + 2/n)
+ *        for an n x n grid (the source well outside the image square). */
 typedef struct {
     int kind;
     int n_views, n_u, n_v;
     double du, dv;
-    double sid, idd;        /* cone only                                    */
+    double sid, idd;        /* cone and fan only                            */
     const double *angles;   /* HOST array [n_views]                         */
 } ct_geometry;
 

@@ -13,6 +13,13 @@ integrals; which rays exist is fixed by the scan geometry.  Conventions:
     (a, b) at Q = C + u_a e_u + v_b e_v with u_a = (a - (Nu-1)/2) du and
     v_b = (b - (Nv-1)/2) dv; ray S + t (Q - S).  Rays ordered
     [view][row b][column a].
+  * 2D fan beam (the acquisition of Sec. IV-A): the plane z = 0 of the
+    cone geometry; view j at angle phi_j = j * span / V; source
+    S = D_so (cos phi, sin phi); detector centre C = -D_od (cos phi,
+    sin phi); axis e_u = (-sin phi, cos phi); bin a at Q = C + u_a e_u,
+    u_a = (a - (K-1)/2) du; ray S + t (Q - S).  Rays ordered [view][bin].
+    The paper does not give the source and detector distances; the cone
+    world geometry's are used.
 """
 import numpy as np
 
@@ -51,11 +58,30 @@ def cone3d_rays(n_views, nu, nv, du, dv, dso, dod, span=2 * np.pi,
     return np.concatenate(p0), np.concatenate(d)
 
 
+def fan2d_rays(n_views, n_bins, du, dso, dod, span=2 * np.pi, views=None):
+    views = np.arange(n_views) if views is None else np.atleast_1d(views)
+    p0, d = [], []
+    for j in views:
+        ph = j * (span / n_views)
+        c, s = np.cos(ph), np.sin(ph)
+        S = np.array([dso * c, dso * s])
+        C = np.array([-dod * c, -dod * s])
+        eu = np.array([-s, c])
+        ua = (np.arange(n_bins) - (n_bins - 1) / 2.0) * du
+        Q = C[None, :] + ua[:, None] * eu[None, :]
+        d.append(Q - S[None, :])
+        p0.append(np.tile(S, (n_bins, 1)))
+    return np.concatenate(p0), np.concatenate(d)
+
+
 def problem_rays(problem, views=None):
     """All rays of a configuration (any object with the Problem fields)."""
     if problem.geometry == "par2d":
         return par2d_rays(problem.n_views, problem.n_u, problem.du,
                           problem.view_span, views)
+    if problem.geometry == "fan2d":
+        return fan2d_rays(problem.n_views, problem.n_u, problem.du,
+                          problem.dso, problem.dod, problem.view_span, views)
     return cone3d_rays(problem.n_views, problem.n_u, problem.n_v, problem.du,
                        problem.dv, problem.dso, problem.dod,
                        problem.view_span, views)

@@ -72,15 +72,15 @@ class Problem:
     name: str
     dim: int
     N: int
-    geometry: str               # "par2d" or "cone3d"
+    geometry: str               # "par2d", "fan2d" or "cone3d"
     n_views: int
     view_span: float            # radians covered by the views (endpoint excluded)
     n_u: int
     n_v: int                    # 1 in 2D
     du: float
     dv: float
-    dso: float = 0.0            # source-to-isocentre (cone)
-    dod: float = 0.0            # isocentre-to-detector (cone)
+    dso: float = 0.0            # source-to-isocentre (fan, cone)
+    dod: float = 0.0            # isocentre-to-detector (fan, cone)
     n_ellipses: int = 10
     photons: float = 0.0        # 0 = noiseless
     arch: INRArch = None
@@ -187,7 +187,20 @@ C4 = Problem(
     steps=1000, mlp_dtype="bf16", chunk_points=1 << 20,
     seed_phantom=1004, seed_noise=2004, seed_init=3004, seed_sampler=4004)
 
-CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4}
+# 2D fan beam, the acquisition of Sec. IV-A: 512^2, 180 views over 360 deg,
+# 512 bins over the cone world geometry's 3.1-unit detector at its source
+# and detector distances; 10 random ellipses (standing in for the FORBILD
+# phantom), Poisson noise at 1e5 photons; FFN 2 -> 512 Fourier features +
+# 4 x 256 ReLU -> 1 in BF16; |I| = n/16 (the paper's 2D minibatch).
+C6 = Problem(
+    name="fan2d-512-ffn", dim=2, N=512, geometry="fan2d", n_views=180,
+    view_span=2 * math.pi, n_u=512, n_v=1, du=CONE_DET_WIDTH / 512,
+    dv=CONE_DET_WIDTH / 512, dso=CONE_DSO, dod=CONE_DOD, n_ellipses=10,
+    photons=1e5, arch=_ffn(2, 256, 256, 4), k_frac=1.0 / 16, lr=1e-3,
+    steps=5000, mlp_dtype="bf16",
+    seed_phantom=1006, seed_noise=2006, seed_init=3006, seed_sampler=4006)
+
+CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c6": C6}
 
 
 # C5, the serving mix: request kinds uniform over {2D-256, 2D-512, 3D-128,
@@ -233,6 +246,17 @@ def cone_problem(N: int, n_views: int, det: int, **kw) -> Problem:
     base = dict(name=f"cone3d-{N}", dim=3, N=N, geometry="cone3d",
                 n_views=n_views, view_span=2 * math.pi, n_u=det, n_v=det,
                 du=CONE_DET_WIDTH / det, dv=CONE_DET_WIDTH / det,
+                dso=CONE_DSO, dod=CONE_DOD)
+    base.update(kw)
+    return Problem(**base)
+
+
+def fan2d_problem(N: int, n_views: int, n_bins: int, **kw) -> Problem:
+    """A fan-beam problem on the cone world geometry's plane z = 0 (views
+    over 360 deg, n_bins over the 3.1-unit detector)."""
+    base = dict(name=f"fan2d-{N}", dim=2, N=N, geometry="fan2d",
+                n_views=n_views, view_span=2 * math.pi, n_u=n_bins, n_v=1,
+                du=CONE_DET_WIDTH / n_bins, dv=CONE_DET_WIDTH / n_bins,
                 dso=CONE_DSO, dod=CONE_DOD)
     base.update(kw)
     return Problem(**base)

@@ -32,7 +32,7 @@ static void build_tables(const ct_geometry &g, int N, std::vector<ColGeom> &cols
         vg.cs = cs;
         vg.sn = sn;
         vg.any_x = vg.any_y = 0;
-        if (g.kind == INRCT_CONE3D) {
+        if (g.kind != INRCT_PAR2D) {  // fan (and the in-plane part of cone)
             vg.Sx = g.sid * cs;
             vg.Sy = g.sid * sn;
             vg.Cx = -g.idd * cs;
@@ -47,7 +47,7 @@ static void build_tables(const ct_geometry &g, int N, std::vector<ColGeom> &cols
         for (int a = 0; a < g.n_u; ++a) {
             const double ua = ((double)a - 0.5 * (double)(g.n_u - 1)) * g.du;
             double p0x, p0y, p0z, dx, dy, dz0;
-            if (g.kind == INRCT_CONE3D) {
+            if (g.kind != INRCT_PAR2D) {
                 p0x = vg.Sx;
                 p0y = vg.Sy;
                 p0z = 0.0;
@@ -156,6 +156,28 @@ __device__ __forceinline__ void par_col_range(const GeomDev &g, const ViewGeom &
     *hi = (int)r;
 }
 
+// Fan beam: bins whose ray crosses the in-plane segment p1-p2 (central
+// projection of the end points from the source onto the detector line,
+// widened by 1e-6 bin against rounding, then rounded outwards).  The
+// projection is monotone along the segment because the whole segment lies
+// on the detector's side of the line through the source parallel to it.
+__device__ __forceinline__ void fan_col_range(const GeomDev &g, const ViewGeom &vg,
+                                              double p1x, double p1y, double p2x,
+                                              double p2y, int *lo, int *hi) {
+    const double ax = vg.Sx - vg.Cx, ay = vg.Sy - vg.Cy;
+    const double D1x = p1x - vg.Sx, D1y = p1y - vg.Sy;
+    const double D2x = p2x - vg.Sx, D2y = p2y - vg.Sy;
+    const double u1 = (ax * D1y - ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
+    const double u2 = (ax * D2y - ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
+    const double c = 0.5 * (double)(g.Nu - 1);
+    const double a1 = u1 / g.du + c, a2 = u2 / g.du + c;
+    double l = floor(fmin(a1, a2) - 1e-6), r = ceil(fmax(a1, a2) + 1e-6);
+    if (l < 0) l = 0;
+    if (r > g.Nu - 1) r = g.Nu - 1;
+    *lo = (int)l;
+    *hi = (int)r;
+}
+
 // weight of voxel index `o` in the linear stencil at position F
 __device__ __forceinline__ float stencil_weight(long long F, int o, bool *hit) {
     const int i0 = fx_int(F);
@@ -167,7 +189,7 @@ __device__ __forceinline__ float stencil_weight(long long F, int o, bool *hit) {
     return 0.f;
 }
 
-// (P^T r) at pixel (ix, iy) of a 2D parallel-beam geometry.
+// (P^T r) at pixel (ix, iy) of a 2D parallel- or fan-beam geometry.
 __device__ float bp_pixel_2d(const GeomDev &g, const float *__restrict__ r, int ix,
                              int iy) {
     const double h = g.h;
@@ -181,8 +203,13 @@ __device__ float bp_pixel_2d(const GeomDev &g, const float *__restrict__ r, int 
             if (ypass ? !vg.any_y : !vg.any_x) continue;
             const int s = ypass ? iy : ix, o = ypass ? ix : iy;
             int lo, hi;
-            if (ypass) par_col_range(g, vg, x - h, y, x + h, y, &lo, &hi);
-            else par_col_range(g, vg, x, y - h, x, y + h, &lo, &hi);
+            if (g.kind == INRCT_FAN2D) {
+                if (ypass) fan_col_range(g, vg, x - h, y, x + h, y, &lo, &hi);
+                else fan_col_range(g, vg, x, y - h, x, y + h, &lo, &hi);
+            } else {
+                if (ypass) par_col_range(g, vg, x - h, y, x + h, y, &lo, &hi);
+                else par_col_range(g, vg, x, y - h, x, y + h, &lo, &hi);
+            }
             for (int k = lo; k <= hi; ++k) {
                 const ColGeom c = g.col[(size_t)j * g.Nu + k];
                 if ((c.ypr != 0) != ypass) continue;
@@ -279,7 +306,7 @@ int geom_N(const inrct_geom *g) { return g->N; }
 
 void project(inrct_geom *geom, const float *u, float *z, hipStream_t s) {
     const GeomDev d = geom->dev();
-    if (d.kind == INRCT_PAR2D) {
+    if (d.kind == INRCT_PAR2D || d.kind == INRCT_FAN2D) {
         hipLaunchKernelGGL(k_proj2d, dim3((unsigned)cdiv(d.Nu, 256), d.V), dim3(256),
                            0, s, d, u, z);
         INRCT_CHECK_LAUNCH();
@@ -290,7 +317,7 @@ void project(inrct_geom *geom, const float *u, float *z, hipStream_t s) {
 
 void backproject(inrct_geom *geom, const float *r, float *v, hipStream_t s) {
     const GeomDev d = geom->dev();
-    if (d.kind == INRCT_PAR2D) {
+    if (d.kind == INRCT_PAR2D || d.kind == INRCT_FAN2D) {
         hipLaunchKernelGGL(k_bproj2d, dim3((unsigned)cdiv(d.N, 64), (unsigned)cdiv(d.N, 4)),
                            dim3(256), 0, s, d, r, v);
         INRCT_CHECK_LAUNCH();
@@ -346,6 +373,13 @@ int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, inrct_geom **o
         if (g->kind == INRCT_PAR2D) {
             INRCT_REQUIRE(grid->dim == 2, "PAR2D needs a 2D grid");
             INRCT_REQUIRE(g->n_v == 1, "PAR2D needs n_v == 1");
+        } else if (g->kind == INRCT_FAN2D) {
+            INRCT_REQUIRE(grid->dim == 2, "FAN2D needs a 2D grid");
+            INRCT_REQUIRE(g->n_v == 1, "FAN2D needs n_v == 1");
+            // pixel segments reach sqrt(2) (1 + h) from the centre; the
+            // adjoint's bin range needs the source beyond that
+            INRCT_REQUIRE(g->sid > 1.4143 * (1.0 + 2.0 / grid->n) && g->idd > 0,
+                          "source must lie outside the image");
         } else if (g->kind == INRCT_CONE3D) {
             INRCT_REQUIRE(grid->dim == 3, "CONE3D needs a 3D grid");
             INRCT_REQUIRE(g->sid > 1.8 && g->idd > 0, "source must lie outside the volume");
@@ -366,7 +400,7 @@ int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, inrct_geom **o
             h->dim = grid->dim;
             h->angles.assign(g->angles, g->angles + g->n_views);
             h->g.angles = h->angles.data();
-            if (g->kind == INRCT_PAR2D) {
+            if (g->kind == INRCT_PAR2D || g->kind == INRCT_FAN2D) {
                 std::vector<ColGeom> cols;
                 std::vector<ViewGeom> views;
                 build_tables(h->g, h->N, cols, views);

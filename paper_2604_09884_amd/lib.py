@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libinrct.so")
 
 INRCT_OK = 0
-INRCT_PAR2D, INRCT_CONE3D = 1, 2
+INRCT_PAR2D, INRCT_CONE3D, INRCT_FAN2D = 1, 2, 3
 INRCT_FFN, INRCT_SIREN = 1, 2
 INRCT_FP32, INRCT_BF16 = 0, 1
 INRCT_LS, INRCT_FLS = 0, 1

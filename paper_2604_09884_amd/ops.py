@@ -45,7 +45,10 @@ class Geometry:
         self.angles = np.ascontiguousarray(
             view_angles(problem) if angles is None else np.asarray(angles, np.float64))
         g = L.CtGeometry()
-        g.kind = L.INRCT_PAR2D if problem.geometry == "par2d" else L.INRCT_CONE3D
+        kinds = {"par2d": L.INRCT_PAR2D, "fan2d": L.INRCT_FAN2D, "cone3d": L.INRCT_CONE3D}
+        if problem.geometry not in kinds:
+            raise ValueError("unknown geometry %r" % problem.geometry)
+        g.kind = kinds[problem.geometry]
         g.n_views, g.n_u, g.n_v = len(self.angles), problem.n_u, problem.n_v
         g.du, g.dv, g.sid, g.idd = problem.du, problem.dv, problem.dso, problem.dod
         g.angles = self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -183,10 +183,27 @@ def rays_cone3d(n_views, nu, nv, du, dv, dso, dod, span=2 * math.pi,
     return np.concatenate(out_p), np.concatenate(out_d)
 
 
+def rays_fan2d(n_views, n_bins, du, dso, dod, span=2 * math.pi, views=None):
+    """Fan-beam rays ordered [view][bin]: (S, Q - S), the z = 0 plane of the
+    cone geometry."""
+    views = np.arange(n_views) if views is None else np.asarray(views)
+    ph = views * (span / n_views)
+    u = (np.arange(n_bins) - (n_bins - 1) / 2.0) * du
+    c, s = np.cos(ph)[:, None], np.sin(ph)[:, None]
+    Sx, Sy = dso * c + 0 * u[None, :], dso * s + 0 * u[None, :]
+    Qx, Qy = -dod * c - u[None, :] * s, -dod * s + u[None, :] * c
+    p0 = np.stack([Sx, Sy], -1).reshape(-1, 2)
+    d = np.stack([Qx - Sx, Qy - Sy], -1).reshape(-1, 2)
+    return p0, d
+
+
 def rays(problem: Problem, views=None):
     if problem.geometry == "par2d":
         return rays_par2d(problem.n_views, problem.n_u, problem.du,
                           problem.view_span, views)
+    if problem.geometry == "fan2d":
+        return rays_fan2d(problem.n_views, problem.n_u, problem.du, problem.dso,
+                          problem.dod, problem.view_span, views)
     return rays_cone3d(problem.n_views, problem.n_u, problem.n_v, problem.du,
                        problem.dv, problem.dso, problem.dod,
                        problem.view_span, views)

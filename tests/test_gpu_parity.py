@@ -30,6 +30,9 @@ def _problems():
         ("par2d-ragged", configs.par2d_problem(37, 7, 53)),
         ("cone-small", configs.cone_problem(24, 5, 20).with_(n_v=18, dv=3.1 / 18)),
         ("cone-ragged", configs.cone_problem(19, 3, 70).with_(n_v=9, dv=3.1 / 9)),
+        ("fan-small", configs.fan2d_problem(32, 12, 45)),
+        ("fan-ragged", configs.fan2d_problem(37, 7, 53)),
+        ("fan-wide", configs.fan2d_problem(41, 9, 61, du=5.0 / 61)),
     ]
 
 
@@ -81,6 +84,7 @@ ARCHS = [
     ("ffn2d-128", configs.C1.arch, configs.par2d_problem(45, 20, 67)),
     ("siren2d-256", configs.C2.arch, configs.par2d_problem(41, 20, 61)),
     ("ffn3d-256", configs.C4.arch, configs.cone_problem(13, 6, 20)),
+    ("ffn2d-512", configs.C6.arch, configs.fan2d_problem(45, 20, 67)),
 ]
 
 

@@ -57,6 +57,24 @@ def test_subsampled_step_small_cone():
     assert rel(g, g_ref) <= 1e-4
 
 
+def test_subsampled_step_small_fan():
+    p = configs.fan2d_problem(40, 24, 57, n_ellipses=5, photons=1e5,
+                              arch=configs.C6.arch.__class__("ffn", 2, 32, 10.0, 256, 2),
+                              k_frac=1.0 / 16, lr=1e-3)
+    for dtype, tol in (("fp32", 1e-4), ("bf16", 2e-2)):
+        st, theta, B, y, k = _setup(p, dtype)
+        prob = ostep.Problem(p)
+        st.step(3)
+        idx = osampler.sample_indices(prob.fov, k, p.seed_sampler, 3)
+        g_ref, L_ref, *_ = ostep.grad_estimate(prob, theta, B, y.reshape(-1).astype(np.float64),
+                                               idx)
+        g = host(st.buffer(3, st.model.n_params))
+        say("fan", dtype, "loss", host(st.loss), L_ref, "g rel", rel(g, g_ref))
+        assert abs(host(st.loss) - L_ref) <= (1e-5 if dtype == "fp32" else tol) * L_ref
+        assert rel(g, g_ref) <= tol
+        st.close()
+
+
 def test_c1_fit_final_mse_within_2_percent():
     p = configs.C1
     st, theta, B, y, k = _setup(p, "fp32")
