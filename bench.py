@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--config", default="c4")
     ap.add_argument("--v-mode", default="full", choices=["full", "at_i"])
     ap.add_argument("--mlp-dtype", default=None, choices=[None, "bf16", "fp32"])
+    ap.add_argument("--subsets", type=int, default=1,
+                    help="ordered subsets over views: step t takes the loss over views j "
+                         "with j mod S == t mod S")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve", type=int, default=0, metavar="R",
@@ -241,6 +244,7 @@ def main():
     k = p.k(model.n_fov)
     v_mode = L.INRCT_V_FULL if a.v_mode == "full" else L.INRCT_V_AT_I
     st = ops.GradStepper(model, geom, th, Bd, yd, k, p.lr, seed=p.seed_sampler, v_mode=v_mode)
+    stepper = ops.OrderedSubsets(st, a.subsets) if a.subsets > 1 else st
     torch.cuda.synchronize()
     free1, _ = torch.cuda.mem_get_info()
     log("n_fov %d, k %d, params %d, device memory in use %.2f GB"
@@ -253,14 +257,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     for t in range(a.warmup):
-        st.step(t)
+        stepper.step(t)
     torch.cuda.synchronize()
     log("warmup done (%d steps), loss %.6g" % (a.warmup, float(st.loss)))
     st.enable_timing(max(1, a.steps))
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for t in range(a.steps):
-        st.step(a.warmup + t)
+        stepper.step(a.warmup + t)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     stages = st.stage_ms()
@@ -283,7 +287,8 @@ def main():
                 "avg_launch_ms": e_ms}
     out = {
         "metric": ("grad steps/s at 501^3 cone-beam 20 views" if a.config == "c4"
-                   else "grad steps/s at " + p.name),
+                   else "grad steps/s at " + p.name)
+                  + (" (%d ordered subsets)" % a.subsets if a.subsets > 1 else ""),
         "value": 1e3 / ms_step,
         "unit": "steps/s",
         "n_gpus": 1,
@@ -300,7 +305,7 @@ def main():
         "config": {"workload": p.name, "grid": "%d^%d" % (p.N, p.dim),
                    "views": p.n_views, "detector": "%dx%d" % (p.n_v, p.n_u),
                    "n_fov": model.n_fov, "k": k, "params": model.n_params,
-                   "v_mode": a.v_mode, "parallelism": "single GPU"},
+                   "v_mode": a.v_mode, "subsets": a.subsets, "parallelism": "single GPU"},
         "stages_ms_per_step": {k_: v / a.steps for k_, v in stages.items()},
         "device_mem_gb": (free0 - free1) / 1e9,
         "loss_last": loss,

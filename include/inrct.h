@@ -243,6 +243,19 @@ int inr_ctx_destroy(inr_ctx *ctx);
 int inr_grad_step(inr_ctx *ctx, uint64_t step, double *loss_out,
                   double *gnorm2_out, hipStream_t stream);
 
+/* The same step with the loss restricted to a subset of the views (the
+ * ordered-subsets use of Algorithm 1 noted at the end of Sec. III): P, the
+ * residual and P^T use `geom` and `y` in place of the context's geometry
+ * and data; everything else is inr_grad_step's.  The loss is the subset's
+ * own, 1/2 ||P_S u - y_S||^2 (LS) or its FLS form, not rescaled.  geom:
+ * any geometry on the context's grid with at most as many rays as the
+ * context's geometry (typically the context geometry's views j with
+ * j mod S == s, built from those angles); y: device float [rays of geom],
+ * in geom's ray order.  Caller keeps ownership of both. */
+int inr_grad_step_views(inr_ctx *ctx, uint64_t step, inrct_geom *geom,
+                        const float *y, double *loss_out, double *gnorm2_out,
+                        hipStream_t stream);
+
 /* Stage timing with HIP events recorded on the step's stream, for
  * measurement.  After inr_ctx_enable_timing(ctx, max_steps), each
  * inr_grad_step records events around its stages (slots reused modulo

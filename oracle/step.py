@@ -7,6 +7,8 @@ Steps, in the paper's order:
   4. virtual loss L~ = (n/|I|) sum_{i in I} v_i f_theta(x_i)       (Eq. (3))
   5. grad L~ = (n/|I|) sum_{i in I} v_i grad f_theta(x_i)          (Eq. (2))
 then theta <- Adam(theta, grad L~).
+With ordered subsets, P, y and the loss of steps 1-2 are those of the
+step's view subset (``subset_problem``).
 
 Here P is an explicit sparse matrix (``joseph.problem_matrix``) and step 5 is
 the exact reverse-mode sum of ``inr.vjp`` with cotangent (n/|I|) v_I.
@@ -79,6 +81,25 @@ def grad_step(prob, theta, B, m, vstate, t, y, idx, lr, kind="ls",
     theta2, m2, v2 = adam.adam_update(theta, m, vstate, g, t, lr, beta1,
                                       beta2, eps)
     return theta2, m2, v2, L, float(g @ g)
+
+
+def subset_views(n_views, n_subsets, s):
+    """Ordered subsets over views (end of Sec. III: the gradient may be taken
+    with respect to a subset of the views).  Reading: S interleaved subsets,
+    subset s holding views j with j mod S == s, and step t using subset
+    t mod S."""
+    return np.arange(s, n_views, n_subsets)
+
+
+def subset_problem(prob, views):
+    """The problem restricted to the listed views: the rows of P that belong
+    to them (rays are view-major, so each view's rows are contiguous), in
+    view order.  Returns (Problem, rows); the data of the subset is
+    y[rows]."""
+    views = np.asarray(views, np.int64)
+    per_view = prob.P.shape[0] // prob.cfg.n_views
+    rows = (views[:, None] * per_view + np.arange(per_view)[None, :]).ravel()
+    return Problem(prob.cfg, P=prob.P[rows]), rows
 
 
 def mse(u, u_true, fov):

@@ -202,6 +202,7 @@ struct inr_ctx {
     inrct_step_cfg cfg;
     float *theta = nullptr, *am = nullptr, *av = nullptr;
     const float *B = nullptr, *y = nullptr;
+    int64_t m_cap = 0;  // rays the r buffer holds
     DevBuf u, r, v, g, idx;
     // optional stage timing: events[slot][stage][0=start, 1=end]
     std::vector<hipEvent_t> events;
@@ -267,7 +268,8 @@ int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *c
             c->B = B;
             c->y = y;
             c->u.alloc(sizeof(float) * model->n_grid);
-            c->r.alloc(sizeof(float) * geom_rays(geom));
+            c->m_cap = geom_rays(geom);
+            c->r.alloc(sizeof(float) * c->m_cap);
             c->v.alloc(sizeof(float) * (cfg->v_mode == INRCT_V_FULL ? model->n_grid : cfg->k));
             c->g.alloc(sizeof(float) * model->n_params);
             c->idx.alloc(sizeof(int32_t) * cfg->k);
@@ -329,55 +331,79 @@ int inr_ctx_stage_ms(inr_ctx *c, int n_stages, double *ms_out) {
     });
 }
 
+}  // extern "C"
+
+// One step with projector `geom` and data `y` (the context's own for the
+// plain step, a view subset's for ordered subsets).
+static void grad_step(inr_ctx *c, uint64_t step, inrct_geom *geom, const float *y,
+                      double *loss_out, double *gnorm2_out, hipStream_t s) {
+    const bool timed = c->t_slots > 0;
+    auto mark = [&](int stage, int end) {
+        if (timed) INRCT_CHECK_HIP(hipEventRecord(c->ev(stage, end), s));
+    };
+    inrct_model *m = c->model;
+    const long long k = c->cfg.k;
+    float *u = c->u.as<float>(), *r = c->r.as<float>(), *v = c->v.as<float>();
+    int32_t *idx = c->idx.as<int32_t>();
+    mark(7, 0);
+    // Algorithm 1, step 1: z = P E{f_theta}
+    model_pack(m, c->theta, s);
+    model_zero_outside(m, u, s);
+    mark(0, 0);
+    model_eval_fov(m, c->theta, c->B, u, s);
+    mark(0, 1);
+    mark(1, 0);
+    project(geom, u, r, s);
+    mark(1, 1);
+    // step 2: r = dL/dz, v = P^T r
+    mark(2, 0);
+    residual_loss(geom, c->cfg.loss, r, y, r, loss_out, s);
+    mark(2, 1);
+    // step 3: the index set I
+    mark(3, 0);
+    model_sample(m, c->cfg.seed, step, k, idx, s);
+    mark(3, 1);
+    mark(4, 0);
+    if (c->cfg.v_mode == INRCT_V_FULL) {
+        backproject(geom, r, v, s);
+    } else {
+        backproject_at(geom, r, idx, k, v, s);
+    }
+    mark(4, 1);
+    // steps 4-5: gradient of the virtual loss, Eq. (2)/(3)
+    const double scale = (double)m->n_fov / (double)k;
+    mark(5, 0);
+    model_vjp(m, c->theta, c->B, idx, k, v, c->cfg.v_mode == INRCT_V_AT_I ? 1 : 0, scale,
+              c->g.as<float>(), s, false);
+    mark(5, 1);
+    mark(6, 0);
+    model_adam(m, c->theta, c->am, c->av, c->g.as<float>(), (long long)step + 1, c->cfg.lr,
+               c->cfg.beta1, c->cfg.beta2, c->cfg.eps, gnorm2_out, s);
+    mark(6, 1);
+    mark(7, 1);
+    if (timed) ++c->t_used;
+}
+
+extern "C" {
+
 int inr_grad_step(inr_ctx *c, uint64_t step, double *loss_out, double *gnorm2_out,
                   hipStream_t s) {
     return guarded([&] {
         INRCT_REQUIRE(c, "null context");
-        const bool timed = c->t_slots > 0;
-        auto mark = [&](int stage, int end) {
-            if (timed) INRCT_CHECK_HIP(hipEventRecord(c->ev(stage, end), s));
-        };
-        inrct_model *m = c->model;
-        const long long k = c->cfg.k;
-        float *u = c->u.as<float>(), *r = c->r.as<float>(), *v = c->v.as<float>();
-        int32_t *idx = c->idx.as<int32_t>();
-        mark(7, 0);
-        // Algorithm 1, step 1: z = P E{f_theta}
-        model_pack(m, c->theta, s);
-        model_zero_outside(m, u, s);
-        mark(0, 0);
-        model_eval_fov(m, c->theta, c->B, u, s);
-        mark(0, 1);
-        mark(1, 0);
-        project(c->geom, u, r, s);
-        mark(1, 1);
-        // step 2: r = dL/dz, v = P^T r
-        mark(2, 0);
-        residual_loss(c->geom, c->cfg.loss, r, c->y, r, loss_out, s);
-        mark(2, 1);
-        // step 3: the index set I
-        mark(3, 0);
-        model_sample(m, c->cfg.seed, step, k, idx, s);
-        mark(3, 1);
-        mark(4, 0);
-        if (c->cfg.v_mode == INRCT_V_FULL) {
-            backproject(c->geom, r, v, s);
-        } else {
-            backproject_at(c->geom, r, idx, k, v, s);
-        }
-        mark(4, 1);
-        // steps 4-5: gradient of the virtual loss, Eq. (2)/(3)
-        const double scale = (double)m->n_fov / (double)k;
-        mark(5, 0);
-        model_vjp(m, c->theta, c->B, idx, k, v, c->cfg.v_mode == INRCT_V_AT_I ? 1 : 0, scale,
-                  c->g.as<float>(), s, false);
-        mark(5, 1);
-        mark(6, 0);
-        model_adam(m, c->theta, c->am, c->av, c->g.as<float>(), (long long)step + 1, c->cfg.lr,
-                   c->cfg.beta1, c->cfg.beta2, c->cfg.eps, gnorm2_out, s);
-        mark(6, 1);
-        mark(7, 1);
-        if (timed) ++c->t_used;
+        grad_step(c, step, c->geom, c->y, loss_out, gnorm2_out, s);
+    });
+}
+
+int inr_grad_step_views(inr_ctx *c, uint64_t step, inrct_geom *geom, const float *y,
+                        double *loss_out, double *gnorm2_out, hipStream_t s) {
+    return guarded([&] {
+        INRCT_REQUIRE(c && geom && y, "null argument");
+        INRCT_REQUIRE(geom_dim(geom) == c->model->dim && geom_N(geom) == c->model->N,
+                      "geometry grid differs from the context's");
+        INRCT_REQUIRE(geom_rays(geom) <= c->m_cap,
+                      "geometry has %lld rays, the context holds %lld",
+                      (long long)geom_rays(geom), (long long)c->m_cap);
+        grad_step(c, step, geom, y, loss_out, gnorm2_out, s);
     });
 }
 

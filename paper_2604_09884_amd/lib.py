@@ -94,6 +94,7 @@ def load():
            [P, P, ctypes.POINTER(StepCfg), P, P, P, P, P, ctypes.POINTER(P)])
     _proto(lib, "inr_ctx_destroy", c_int, [P])
     _proto(lib, "inr_grad_step", c_int, [P, c_u64, P, P, P])
+    _proto(lib, "inr_grad_step_views", c_int, [P, c_u64, P, P, P, P, P])
     _proto(lib, "inr_ctx_buffer", c_void_p, [P, c_int])
     _proto(lib, "inr_ctx_enable_timing", c_int, [P, c_int])
     _proto(lib, "inr_ctx_stage_ms", c_int, [P, c_int, ctypes.POINTER(c_double)])
@@ -113,5 +114,5 @@ EXPORTED = [
     "inrct_model_create", "inrct_model_destroy", "inrct_model_n_params",
     "inrct_model_n_fov", "inr_eval_grid", "inr_eval_points", "inr_vjp_subsampled",
     "inrct_sample", "inrct_adam", "inr_ctx_create", "inr_ctx_destroy", "inr_grad_step",
-    "inr_ctx_buffer", "inr_ctx_enable_timing", "inr_ctx_stage_ms",
+    "inr_grad_step_views", "inr_ctx_buffer", "inr_ctx_enable_timing", "inr_ctx_stage_ms",
 ]

@@ -233,6 +233,13 @@ class GradStepper:
         L.check(L.load().inr_grad_step(self.handle, t, _ptr(self.loss), _ptr(self.gnorm2),
                                        _stream()))
 
+    def step_views(self, t: int, geom: "Geometry", y):
+        """Step t with the loss over the views of `geom` (data `y` in its ray
+        order) in place of the context's geometry and data."""
+        _need(y, torch.float32, geom.n_rays, "y")
+        L.check(L.load().inr_grad_step_views(self.handle, t, geom.handle, _ptr(y),
+                                             _ptr(self.loss), _ptr(self.gnorm2), _stream()))
+
     STAGES = ("eval_grid", "project", "residual", "sample", "backproject", "vjp", "adam",
               "step")
 
@@ -262,6 +269,41 @@ class GradStepper:
             self.close()
         except Exception:
             pass
+
+
+def subset_views(n_views: int, n_subsets: int, s: int) -> np.ndarray:
+    """Views of ordered subset s: j with j mod n_subsets == s, ascending."""
+    if not 1 <= n_subsets <= n_views or not 0 <= s < n_subsets:
+        raise ValueError("need 1 <= n_subsets <= n_views and 0 <= s < n_subsets")
+    return np.arange(s, n_views, n_subsets)
+
+
+class OrderedSubsets:
+    """Ordered-subsets stepping (the view-subset use of Algorithm 1): step
+    t takes the loss over subset t mod S of the views, i.e. views j with
+    j mod S == t mod S, with its own geometry and slice of the data, all
+    resident on the device."""
+
+    def __init__(self, stepper: GradStepper, n_subsets: int):
+        p = stepper.geom.problem
+        angles = stepper.geom.angles
+        V = len(angles)
+        y = stepper.y.reshape(V, -1)
+        self.stepper, self.S = stepper, int(n_subsets)
+        self.geoms, self.ys = [], []
+        for s in range(self.S):
+            views = subset_views(V, self.S, s)
+            self.geoms.append(Geometry(p, angles=angles[views]))
+            self.ys.append(y[torch.as_tensor(views, device=y.device)].reshape(-1).contiguous())
+
+    def step(self, t: int):
+        s = t % self.S
+        self.stepper.step_views(t, self.geoms[s], self.ys[s])
+
+    def close(self):
+        for g in self.geoms:
+            g.close()
+        self.geoms, self.ys = [], []
 
 
 def _wrap_device(ptr, numel, dtype, device):

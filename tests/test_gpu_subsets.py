@@ -1,0 +1,77 @@
+"""GPU parity of ordered-subsets stepping (the loss over one subset of the
+views per step) against the oracle, through inr_grad_step_views."""
+import numpy as np
+import pytest
+
+from oracle import sampler as osampler
+from oracle import step as ostep
+from paper_2604_09884_amd import configs, synth
+from tests.gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# SIREN: smooth in theta, so FP32 and FP64 gradients agree at every step
+# (with ReLU, a pre-activation within rounding of zero at some step flips a
+# decision and moves g by ~1e-3; the subset logic does not depend on the
+# architecture).
+ARCH2 = configs.INRArch("siren", 2, 0, 0.0, 128, 3, 30.0)
+ARCH3 = configs.INRArch("siren", 3, 0, 0.0, 128, 3, 30.0)
+
+
+def _cases():
+    return [
+        ("par2d", configs.par2d_problem(40, 30, 57, arch=ARCH2, k_frac=0.25, n_ellipses=5), "ls"),
+        ("fan2d", configs.fan2d_problem(37, 24, 53, arch=ARCH2, k_frac=0.25, n_ellipses=5), "fls"),
+        ("cone3d", configs.cone_problem(16, 10, 20, arch=ARCH3, k_frac=0.1, n_ellipses=5), "ls"),
+    ]
+
+
+def _stepper(p, loss):
+    from paper_2604_09884_amd import lib as L, ops
+    theta, B = synth.init_inr(p.arch, p.seed_init)
+    y = synth.sinogram(p).astype(np.float32)
+    m = ops.Model(p.arch, p.dim, p.N, "fp32", max_k=p.k())
+    g = ops.Geometry(p)
+    Bd = dev(B.ravel() if B.size else np.zeros(1))
+    st = ops.GradStepper(m, g, dev(theta), Bd, dev(y.ravel()), p.k(), p.lr,
+                         seed=p.seed_sampler, loss=L.INRCT_FLS if loss == "fls" else L.INRCT_LS)
+    return st, B, y
+
+
+@pytest.mark.parametrize("name,p,loss", _cases(), ids=[c[0] for c in _cases()])
+def test_ordered_subsets_match_oracle(name, p, loss):
+    from paper_2604_09884_amd import ops
+    st, B, y = _stepper(p, loss)
+    S = 3
+    os_ = ops.OrderedSubsets(st, S)
+    prob = ostep.Problem(p)
+    yv = y.reshape(-1).astype(np.float64)
+    for t in range(4):
+        th = host(st.theta).astype(np.float64)
+        os_.step(t)
+        sub, rows = ostep.subset_problem(prob, ostep.subset_views(p.n_views, S, t % S))
+        idx = osampler.sample_indices(prob.fov, st.k, p.seed_sampler, t)
+        g_ref, L_ref, *_ = ostep.grad_estimate(sub, th, B, yv[rows], idx, loss)
+        g = host(st.buffer(3, st.model.n_params))
+        say(name, "t", t, "loss", float(host(st.loss)), L_ref, "g rel", rel(g, g_ref))
+        assert abs(float(host(st.loss)) - L_ref) <= 1e-5 * abs(L_ref)
+        assert rel(g, g_ref) <= 1e-4
+    os_.close()
+    st.close()
+
+
+def test_one_subset_is_the_plain_step_and_oversized_geometry_is_refused():
+    from paper_2604_09884_amd import ops
+    p = _cases()[0][1]
+    a, _, _ = _stepper(p, "ls")
+    b, _, _ = _stepper(p, "ls")
+    one = ops.OrderedSubsets(b, 1)
+    for t in range(3):
+        a.step(t)
+        one.step(t)
+        assert np.array_equal(host(a.theta), host(b.theta))
+        assert float(host(a.loss)) == float(host(b.loss))
+    big = ops.Geometry(p.with_(n_views=p.n_views + 1))
+    with pytest.raises(Exception, match="rays"):
+        a.step_views(3, big, dev(np.zeros(big.n_rays, np.float32)))
+    one.close()
