@@ -5,29 +5,29 @@
 
 namespace inrct {
 
-// 2D parallel beam: one record per (view, bin), 32.32 fixed point.
-struct ColGeom {
-    double t0;     // ray parameter at slice 0
-    double inv;    // 1 / d_axis
-    double p0z;    // unused in 2D
-    double dz0;    // unused in 2D
-    double dxy2;   // squared length of the ray direction
-    long long F0o; // 32.32 fixed-point phi_other at slice 0
-    long long dFo; // per-slice increment of phi_other
-    int ypr;       // 1: y is the principal axis
-    int pad;
+// 2D parallel and fan beam: one record per (view, detector bin).  The
+// interpolation position of the ray's non-principal coordinate at slice s
+// is the exact 32.32 fixed-point integer F0 + s dF, in P and in P^T.
+struct Col2D {
+    long long F0, dF;
 };
 
-struct ViewGeom {
-    double Sx, Sy, Cx, Cy, eux, euy, cs, sn;
-    int any_y, any_x;
+// Per view, in single precision, what the adjoint needs to find the
+// candidate bins of a pixel: parallel beam uses the detector axis (eux,
+// euy); fan beam the source S, S - C and the detector axis.  Bins are split
+// by principal axis: [0, ysplit) are y-principal iff yfirst, [ysplit, Nu)
+// the other way (a fan narrower than 90 degrees has at most one change).
+struct View2D {
+    float sx, sy, ax, ay, eux, euy;
+    int ysplit, yfirst;
 };
 
 struct GeomDev {
     int kind, N, V, Nu, Nv;
     double h, du, dv;
-    const ColGeom *col;   // [V][Nu]
-    const ViewGeom *view; // [V]
+    const Col2D *col;    // [V][Nu]
+    const float *step;   // [V][Nu] slice step length h |d| / |d_axis|
+    const View2D *view;  // [V]
 };
 
 // 3D cone beam: one record per (view, detector column), 24.40 fixed point.
@@ -63,7 +63,7 @@ struct inrct_geom {
     ct_geometry g;
     int N = 0, dim = 0;
     std::vector<double> angles;
-    inrct::DevBuf cols, views, q, partials;
+    inrct::DevBuf cols, steps, views, q, partials;
     int n_partials = 0;
     // cone beam
     inrct::DevBuf ccols, cviews, ut;
@@ -78,8 +78,9 @@ struct inrct_geom {
         d.h = 2.0 / N;
         d.du = g.du;
         d.dv = g.dv;
-        d.col = cols.as<inrct::ColGeom>();
-        d.view = views.as<inrct::ViewGeom>();
+        d.col = cols.as<inrct::Col2D>();
+        d.step = steps.as<float>();
+        d.view = views.as<inrct::View2D>();
         return d;
     }
     inrct::ConeDev cone() const {

@@ -2079,6 +2079,12 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
                 }
                 m->ntiles = (int)tiles2.size();
                 upload(m->tiles, tiles2);
+                // split-K slices of 2048 points, shortened (to no less than
+                // 512) when the chunk is too small to give every CU a block
+                const long long want = cdiv((long long)m->n_cu, (long long)m->ntiles);
+                const long long ks = cdiv(cdiv(P, want), 256) * 256;
+                m->kslice = (int)std::min<long long>(2048, std::max<long long>(512, ks));
+                m->nks = (int)cdiv(P, m->kslice);
                 m->part.alloc((size_t)m->nks * m->ntiles * kDwPart * sizeof(float));
             }
             // dW GEMM tiles: layer l = 1..L+1, delta rows M, inputs R (+ bias col)

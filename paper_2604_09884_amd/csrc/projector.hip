@@ -1,13 +1,13 @@
-// 2D parallel-beam Joseph projector P, its voxel-driven exact transpose P^T,
-// the data-fidelity residuals (Sec. II, Sec. III of the paper) and the
-// geometry handle.  The cone-beam kernels are in cone.hip.
+// 2D parallel- and fan-beam Joseph projector P, its voxel-driven exact
+// transpose P^T, the data-fidelity residuals (Sec. II, Sec. III of the
+// paper) and the geometry handle.  The cone-beam kernels are in cone.hip.
 //
 // Geometry is reduced on the host, in float64, to one record per (view,
-// detector bin): the principal axis, 1/d_axis, the ray parameter at the
-// first slice and the interpolation position of the in-plane "other"
-// coordinate as a 32.32 fixed-point start value and per-slice increment.
-// Because the interpolation position at slice s is the exact integer
-// F0 + s * dF in both kernels, P^T applies exactly the weights P applies.
+// detector bin): the interpolation position of the ray's non-principal
+// coordinate as a 32.32 fixed-point start value and per-slice increment,
+// and the slice step length.  Because the interpolation position at slice
+// s is the exact integer F0 + s * dF in both kernels, P^T applies exactly
+// the weights P applies.
 #include <math.h>
 
 #include "geom.h"
@@ -18,79 +18,93 @@ static const double kFix = 4294967296.0;       // 2^32
 static const float kInvFix = 2.3283064365386963e-10f;  // 2^-32
 
 // ------------------------------------------------------------- host tables
-static void build_tables(const ct_geometry &g, int N, std::vector<ColGeom> &cols,
-                         std::vector<ViewGeom> &views) {
+// Per (view, bin) ray geometry in float64, before it is reduced to the
+// device tables.
+struct RayGeom {
+    long long F0, dF;  // 32.32 fixed point phi_other at slice 0, per slice
+    double step;       // h |d| / |d_axis|
+    int ypr;           // 1: y is the principal axis
+};
+
+static void build_tables(const ct_geometry &g, int N, std::vector<Col2D> &cols,
+                         std::vector<float> &steps, std::vector<View2D> &views) {
     const double h = 2.0 / N;
     const double c0 = -1.0 + 0.5 * h;
     const double tau = 1e-9;
+    const bool fan = g.kind != INRCT_PAR2D;
     cols.resize((size_t)g.n_views * g.n_u);
+    steps.resize(cols.size());
     views.resize(g.n_views);
+    std::vector<RayGeom> rg(g.n_u);
     for (int j = 0; j < g.n_views; ++j) {
         const double th = g.angles[j];
         const double cs = cos(th), sn = sin(th);
-        ViewGeom &vg = views[j];
-        vg.cs = cs;
-        vg.sn = sn;
-        vg.any_x = vg.any_y = 0;
-        if (g.kind != INRCT_PAR2D) {  // fan (and the in-plane part of cone)
-            vg.Sx = g.sid * cs;
-            vg.Sy = g.sid * sn;
-            vg.Cx = -g.idd * cs;
-            vg.Cy = -g.idd * sn;
-            vg.eux = -sn;
-            vg.euy = cs;
-        } else {
-            vg.Sx = vg.Sy = vg.Cx = vg.Cy = 0.0;
-            vg.eux = cs;
-            vg.euy = sn;
-        }
+        // fan: source S, detector centre C, detector axis e_u (the in-plane
+        // part of the cone geometry); parallel: rays (-sin, cos) through
+        // u (cos, sin)
+        const double Sx = g.sid * cs, Sy = g.sid * sn, Cx = -g.idd * cs, Cy = -g.idd * sn;
+        const double eux = fan ? -sn : cs, euy = fan ? cs : sn;
         for (int a = 0; a < g.n_u; ++a) {
             const double ua = ((double)a - 0.5 * (double)(g.n_u - 1)) * g.du;
-            double p0x, p0y, p0z, dx, dy, dz0;
-            if (g.kind != INRCT_PAR2D) {
-                p0x = vg.Sx;
-                p0y = vg.Sy;
-                p0z = 0.0;
-                dx = vg.Cx - vg.Sx + ua * vg.eux;
-                dy = vg.Cy - vg.Sy + ua * vg.euy;
-                dz0 = 0.0;
+            double p0x, p0y, dx, dy;
+            if (fan) {
+                p0x = Sx;
+                p0y = Sy;
+                dx = Cx - Sx + ua * eux;
+                dy = Cy - Sy + ua * euy;
             } else {
                 p0x = ua * cs;
                 p0y = ua * sn;
-                p0z = 0.0;
                 dx = -sn;
                 dy = cs;
-                dz0 = 0.0;
             }
-            ColGeom &c = cols[(size_t)j * g.n_u + a];
-            c.ypr = fabs(dy) >= (1.0 - tau) * fabs(dx) ? 1 : 0;
-            const double dax = c.ypr ? dy : dx;
-            const double dot = c.ypr ? dx : dy;
-            const double pax = c.ypr ? p0y : p0x;
-            const double pot = c.ypr ? p0x : p0y;
-            c.inv = 1.0 / dax;
-            c.t0 = (c0 - pax) * c.inv;
-            const double phi0 = (pot + c.t0 * dot + 1.0) / h - 0.5;
-            c.F0o = llrint(phi0 * kFix);
-            c.dFo = llrint(dot * c.inv * kFix);
-            c.p0z = p0z;
-            c.dz0 = dz0;
-            c.dxy2 = dx * dx + dy * dy;
-            c.pad = 0;
-            if (c.ypr) vg.any_y = 1; else vg.any_x = 1;
+            RayGeom &r = rg[a];
+            r.ypr = fabs(dy) >= (1.0 - tau) * fabs(dx) ? 1 : 0;
+            const double dax = r.ypr ? dy : dx;
+            const double dot = r.ypr ? dx : dy;
+            const double pax = r.ypr ? p0y : p0x;
+            const double pot = r.ypr ? p0x : p0y;
+            const double inv = 1.0 / dax;
+            const double t0 = (c0 - pax) * inv;
+            const double phi0 = (pot + t0 * dot + 1.0) / h - 0.5;
+            r.F0 = llrint(phi0 * kFix);
+            r.dF = llrint(dot * inv * kFix);
+            r.step = h * sqrt(dx * dx + dy * dy) * fabs(inv);
+        }
+        int changes = 0, split = g.n_u;
+        for (int a = 1; a < g.n_u; ++a)
+            if (rg[a].ypr != rg[a - 1].ypr) {
+                ++changes;
+                split = a;
+            }
+        if (changes > 1) {
+            set_error("view %d: the fan crosses two principal-axis boundaries (wider than 90 "
+                      "degrees)", j);
+            throw Error{INRCT_EINVAL};
+        }
+        View2D &vg = views[j];
+        vg.sx = (float)(fan ? Sx : 0.0);
+        vg.sy = (float)(fan ? Sy : 0.0);
+        vg.ax = (float)(fan ? Sx - Cx : 0.0);
+        vg.ay = (float)(fan ? Sy - Cy : 0.0);
+        vg.eux = (float)eux;
+        vg.euy = (float)euy;
+        vg.ysplit = split;
+        vg.yfirst = rg[0].ypr;
+        for (int a = 0; a < g.n_u; ++a) {
+            cols[(size_t)j * g.n_u + a] = Col2D{rg[a].F0, rg[a].dF};
+            steps[(size_t)j * g.n_u + a] = (float)rg[a].step;
         }
     }
 }
 
 // --------------------------------------------------------- device helpers
-__device__ __forceinline__ float ray_step2d(const GeomDev &g, const ColGeom &c) {
-#pragma clang fp contract(off)
-    return (float)(g.h * sqrt(c.dxy2) * fabs(c.inv));
-}
-
 __device__ __forceinline__ int fx_int(long long F) { return (int)(F >> 32); }
 __device__ __forceinline__ float fx_frac(long long F) {
     return (float)(unsigned int)(F & 0xffffffffLL) * kInvFix;
+}
+__device__ __forceinline__ bool bin_ypr(const View2D &vg, int a) {
+    return (a < vg.ysplit) == (vg.yfirst != 0);
 }
 
 // Slices s in [0, N) whose interpolation index floor(phi(s)) can touch the
@@ -118,126 +132,177 @@ __device__ __forceinline__ void slice_range(long long F0, long long dF, int N,
 }
 
 // ----------------------------------------------------------- forward, 2D
-__global__ __launch_bounds__(256) void k_proj2d(GeomDev g, const float *__restrict__ u,
-                                                float *__restrict__ z) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y;
-    if (k >= g.Nu) return;
-    const ColGeom c = g.col[(size_t)j * g.Nu + k];
-    const int N = g.N;
-    int lo, hi;
-    slice_range(c.F0o, c.dFo, N, &lo, &hi);
-    long long F = c.F0o + (long long)lo * c.dFo;
-    float acc = 0.f;
-    for (int s = lo; s <= hi; ++s, F += c.dFo) {
-        const int io = fx_int(F);
-        const float w = fx_frac(F);
-        float v0 = 0.f, v1 = 0.f;
-        const size_t base = c.ypr ? (size_t)s * N : (size_t)s;
-        const size_t str = c.ypr ? 1 : (size_t)N;
-        if ((unsigned)io < (unsigned)N) v0 = u[base + (size_t)io * str];
-        if ((unsigned)(io + 1) < (unsigned)N) v1 = u[base + (size_t)(io + 1) * str];
-        acc += (1.f - w) * v0 + w * v1;
+// ut = u transposed ([x][y]), so that x-principal rays read rows too.
+__global__ __launch_bounds__(256) void k_transpose2d(const float *__restrict__ u,
+                                                     float *__restrict__ ut, int N) {
+    __shared__ float t[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    for (int k = 0; k < 32; k += 8) {
+        const int x = x0 + tx, y = y0 + ty + k;
+        if (x < N && y < N) t[ty + k][tx] = u[(size_t)y * N + x];
     }
-    z[(size_t)j * g.Nu + k] = acc * ray_step2d(g, c);
+    __syncthreads();
+    for (int k = 0; k < 32; k += 8) {
+        const int y = y0 + tx, x = x0 + ty + k;
+        if (x < N && y < N) ut[(size_t)x * N + y] = t[tx][ty + k];
+    }
+}
+
+// A workgroup covers 64 consecutive bins of one view (one bin per lane);
+// its four waves integrate four consecutive quarters of every ray's slice
+// range, and the quarters are added in order.  At slice s a y-principal ray
+// reads row s of u, an x-principal ray row s of ut, so neighbouring bins
+// read neighbouring addresses either way.
+__global__ __launch_bounds__(256) void k_proj2d(GeomDev g, const float *__restrict__ u,
+                                                const float *__restrict__ ut,
+                                                float *__restrict__ z) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = blockIdx.x * 64 + lane;
+    const int j = blockIdx.y;
+    const int N = g.N;
+    float acc = 0.f;
+    if (a < g.Nu) {
+        const Col2D c = g.col[(size_t)j * g.Nu + a];
+        const float *src = bin_ypr(g.view[j], a) ? u : ut;
+        int lo, hi;
+        slice_range(c.F0, c.dF, N, &lo, &hi);
+        const int q = (hi - lo + 4) >> 2;  // ceil(len / 4), len = hi - lo + 1
+        const int s0 = lo + w * q, s1 = min(hi, s0 + q - 1);
+        long long F = c.F0 + (long long)s0 * c.dF;
+        for (int s = s0; s <= s1; ++s, F += c.dF) {
+            const int io = fx_int(F);
+            const float wt = fx_frac(F);
+            const float *row = src + (size_t)s * N;
+            const float v0 = (unsigned)io < (unsigned)N ? row[io] : 0.f;
+            const float v1 = (unsigned)(io + 1) < (unsigned)N ? row[io + 1] : 0.f;
+            acc += (1.f - wt) * v0 + wt * v1;
+        }
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && a < g.Nu)
+        z[(size_t)j * g.Nu + a] =
+            (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) *
+            g.step[(size_t)j * g.Nu + a];
 }
 
 // ------------------------------------------------ adjoint (gather) helpers
-__device__ __forceinline__ void par_col_range(const GeomDev &g, const ViewGeom &vg,
-                                              double p1x, double p1y, double p2x,
-                                              double p2y, int *lo, int *hi) {
-    const double s1 = p1x * vg.cs + p1y * vg.sn, s2 = p2x * vg.cs + p2y * vg.sn;
-    const double c = 0.5 * (double)(g.Nu - 1);
-    const double a1 = s1 / g.du + c, a2 = s2 / g.du + c;
-    double l = floor(fmin(a1, a2)), r = ceil(fmax(a1, a2));
-    if (l < 0) l = 0;
-    if (r > g.Nu - 1) r = g.Nu - 1;
+// Bins whose ray crosses the in-plane segment p1-p2, in single precision
+// and widened by 0.01 bin, far above its rounding error: every candidate is
+// then tested exactly on the fixed-point stencil, so an extra candidate
+// costs time but never changes a sum.  Parallel beam: the segment's
+// projection on the detector axis.  Fan beam: the central projection of its
+// end points from the source onto the detector line (monotone along the
+// segment, since the segment lies on the detector's side of the line
+// through the source parallel to the detector).
+template <bool FAN>
+__device__ __forceinline__ void cand_bins(const GeomDev &g, const View2D &vg, float p1x,
+                                          float p1y, float p2x, float p2y, float inv_du,
+                                          int *lo, int *hi) {
+    float u1, u2;
+    if (FAN) {
+        const float D1x = p1x - vg.sx, D1y = p1y - vg.sy;
+        const float D2x = p2x - vg.sx, D2y = p2y - vg.sy;
+        u1 = (vg.ax * D1y - vg.ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
+        u2 = (vg.ax * D2y - vg.ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
+    } else {
+        u1 = p1x * vg.eux + p1y * vg.euy;
+        u2 = p2x * vg.eux + p2y * vg.euy;
+    }
+    const float c = 0.5f * (float)(g.Nu - 1);
+    const float a1 = u1 * inv_du + c, a2 = u2 * inv_du + c;
+    float l = floorf(fminf(a1, a2) - 0.01f), r = ceilf(fmaxf(a1, a2) + 0.01f);
+    l = fmaxf(l, 0.f);
+    r = fminf(r, (float)(g.Nu - 1));
     *lo = (int)l;
     *hi = (int)r;
 }
 
-// Fan beam: bins whose ray crosses the in-plane segment p1-p2 (central
-// projection of the end points from the source onto the detector line,
-// widened by 1e-6 bin against rounding, then rounded outwards).  The
-// projection is monotone along the segment because the whole segment lies
-// on the detector's side of the line through the source parallel to it.
-__device__ __forceinline__ void fan_col_range(const GeomDev &g, const ViewGeom &vg,
-                                              double p1x, double p1y, double p2x,
-                                              double p2y, int *lo, int *hi) {
-    const double ax = vg.Sx - vg.Cx, ay = vg.Sy - vg.Cy;
-    const double D1x = p1x - vg.Sx, D1y = p1y - vg.Sy;
-    const double D2x = p2x - vg.Sx, D2y = p2y - vg.Sy;
-    const double u1 = (ax * D1y - ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
-    const double u2 = (ax * D2y - ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
-    const double c = 0.5 * (double)(g.Nu - 1);
-    const double a1 = u1 / g.du + c, a2 = u2 / g.du + c;
-    double l = floor(fmin(a1, a2) - 1e-6), r = ceil(fmax(a1, a2) + 1e-6);
-    if (l < 0) l = 0;
-    if (r > g.Nu - 1) r = g.Nu - 1;
-    *lo = (int)l;
-    *hi = (int)r;
-}
-
-// weight of voxel index `o` in the linear stencil at position F
-__device__ __forceinline__ float stencil_weight(long long F, int o, bool *hit) {
-    const int i0 = fx_int(F);
-    const float w = fx_frac(F);
-    *hit = true;
-    if (i0 == o) return 1.f - w;
-    if (i0 == o - 1) return w;
-    *hit = false;
-    return 0.f;
-}
-
-// (P^T r) at pixel (ix, iy) of a 2D parallel- or fan-beam geometry.
-__device__ float bp_pixel_2d(const GeomDev &g, const float *__restrict__ r, int ix,
-                             int iy) {
-    const double h = g.h;
-    const double x = -1.0 + (ix + 0.5) * h, y = -1.0 + (iy + 0.5) * h;
+// The part of (P^T r) at pixel (ix, iy) from views [j0, j1): rs is the
+// step-weighted residual r * step.  Views in order; per view the
+// y-principal bins, then the x-principal ones, each in ascending order.
+template <bool FAN>
+__device__ float bp_pixel_2d(const GeomDev &g, const float *__restrict__ rs, int ix, int iy,
+                             int j0, int j1) {
+    const float h = (float)g.h;
+    const float x = (float)(-1.0 + (ix + 0.5) * g.h), y = (float)(-1.0 + (iy + 0.5) * g.h);
+    const float inv_du = (float)(1.0 / g.du);
+    const int Nu = g.Nu;
     float acc = 0.f;
-    for (int j = 0; j < g.V; ++j) {
-        const ViewGeom vg = g.view[j];
-        const float *rj = r + (size_t)j * g.Nu;
+    for (int j = j0; j < j1; ++j) {
+        const View2D vg = g.view[j];
+        const float *rj = rs + (size_t)j * Nu;
+        const Col2D *cj = g.col + (size_t)j * Nu;
         for (int pass = 0; pass < 2; ++pass) {
             const bool ypass = pass == 0;
-            if (ypass ? !vg.any_y : !vg.any_x) continue;
+            // the run of bins with this principal axis
+            int blo = (ypass == (vg.yfirst != 0)) ? 0 : vg.ysplit;
+            int bhi = (ypass == (vg.yfirst != 0)) ? vg.ysplit - 1 : Nu - 1;
+            if (blo > bhi) continue;
             const int s = ypass ? iy : ix, o = ypass ? ix : iy;
             int lo, hi;
-            if (g.kind == INRCT_FAN2D) {
-                if (ypass) fan_col_range(g, vg, x - h, y, x + h, y, &lo, &hi);
-                else fan_col_range(g, vg, x, y - h, x, y + h, &lo, &hi);
-            } else {
-                if (ypass) par_col_range(g, vg, x - h, y, x + h, y, &lo, &hi);
-                else par_col_range(g, vg, x, y - h, x, y + h, &lo, &hi);
-            }
-            for (int k = lo; k <= hi; ++k) {
-                const ColGeom c = g.col[(size_t)j * g.Nu + k];
-                if ((c.ypr != 0) != ypass) continue;
-                bool hit;
-                const float w = stencil_weight(c.F0o + (long long)s * c.dFo, o, &hit);
-                if (hit) acc += w * ray_step2d(g, c) * rj[k];
+            if (ypass) cand_bins<FAN>(g, vg, x - h, y, x + h, y, inv_du, &lo, &hi);
+            else cand_bins<FAN>(g, vg, x, y - h, x, y + h, inv_du, &lo, &hi);
+            lo = max(lo, blo);
+            hi = min(hi, bhi);
+            for (int a = lo; a <= hi; ++a) {
+                const Col2D c = cj[a];
+                const long long F = c.F0 + (long long)s * c.dF;
+                const int i0 = fx_int(F);
+                const float wt = fx_frac(F);
+                if (i0 == o) acc += (1.f - wt) * rj[a];
+                else if (i0 == o - 1) acc += wt * rj[a];
             }
         }
     }
     return acc;
 }
 
-__global__ __launch_bounds__(256) void k_bproj2d(GeomDev g, const float *__restrict__ r,
-                                                 float *__restrict__ v) {
-    const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (ix >= g.N || iy >= g.N) return;
-    v[(size_t)iy * g.N + ix] = bp_pixel_2d(g, r, ix, iy);
+// rs = r * step length (applied on the ray side of P^T)
+__global__ __launch_bounds__(256) void k_prescale2d(GeomDev g, const float *__restrict__ r,
+                                                    float *__restrict__ rs) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < (int64_t)g.V * g.Nu) rs[i] = r[i] * g.step[i];
 }
 
-__global__ __launch_bounds__(256) void k_bproj_at(GeomDev g, const float *__restrict__ r,
+// A workgroup covers an 8 x 8 patch of pixels (one per lane); its four
+// waves gather four consecutive quarters of the views, added in order.
+template <bool FAN>
+__global__ __launch_bounds__(256) void k_bproj2d(GeomDev g, const float *__restrict__ rs,
+                                                 float *__restrict__ v) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ix = blockIdx.x * 8 + (lane & 7);
+    const int iy = blockIdx.y * 8 + (lane >> 3);
+    const bool in = ix < g.N && iy < g.N;
+    const int q = (g.V + 3) >> 2;
+    const int j0 = min(g.V, w * q), j1 = min(g.V, j0 + q);
+    part[w][lane] = in ? bp_pixel_2d<FAN>(g, rs, ix, iy, j0, j1) : 0.f;
+    __syncthreads();
+    if (w == 0 && in)
+        v[(size_t)iy * g.N + ix] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+template <bool FAN>
+__global__ __launch_bounds__(256) void k_bproj_at(GeomDev g, const float *__restrict__ rs,
                                                   const int32_t *__restrict__ idx,
                                                   int64_t k, float *__restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= k) return;
     const int64_t q = idx[t];
     const int N = g.N;
-    out[t] = bp_pixel_2d(g, r, (int)(q % N), (int)((q / N) % N));
+    const int ix = (int)(q % N), iy = (int)((q / N) % N);
+    // the same view quarters, added in the same order, as k_bproj2d
+    const int qv = (g.V + 3) >> 2;
+    float acc = 0.f;
+    for (int w = 0; w < 4; ++w) {
+        const int j0 = min(g.V, w * qv), j1 = min(g.V, j0 + qv);
+        const float p = bp_pixel_2d<FAN>(g, rs, ix, iy, j0, j1);
+        acc = w == 0 ? p : acc + p;
+    }
+    out[t] = acc;
 }
 
 // ---------------------------------------------------------------- residual
@@ -307,19 +372,36 @@ int geom_N(const inrct_geom *g) { return g->N; }
 void project(inrct_geom *geom, const float *u, float *z, hipStream_t s) {
     const GeomDev d = geom->dev();
     if (d.kind == INRCT_PAR2D || d.kind == INRCT_FAN2D) {
-        hipLaunchKernelGGL(k_proj2d, dim3((unsigned)cdiv(d.Nu, 256), d.V), dim3(256),
-                           0, s, d, u, z);
+        float *ut = geom->ut.as<float>();
+        hipLaunchKernelGGL(k_transpose2d, dim3((unsigned)cdiv(d.N, 32), (unsigned)cdiv(d.N, 32)),
+                           dim3(256), 0, s, u, ut, d.N);
+        INRCT_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_proj2d, dim3((unsigned)cdiv(d.Nu, 64), d.V), dim3(256),
+                           0, s, d, u, ut, z);
         INRCT_CHECK_LAUNCH();
     } else {
         cone_project(geom, u, z, s);
     }
 }
 
+static const float *prescale2d(inrct_geom *geom, const float *r, hipStream_t s) {
+    const GeomDev d = geom->dev();
+    float *rs = geom->q.as<float>();
+    hipLaunchKernelGGL(k_prescale2d, dim3((unsigned)cdiv((int64_t)d.V * d.Nu, 256)), dim3(256),
+                       0, s, d, r, rs);
+    INRCT_CHECK_LAUNCH();
+    return rs;
+}
+
 void backproject(inrct_geom *geom, const float *r, float *v, hipStream_t s) {
     const GeomDev d = geom->dev();
     if (d.kind == INRCT_PAR2D || d.kind == INRCT_FAN2D) {
-        hipLaunchKernelGGL(k_bproj2d, dim3((unsigned)cdiv(d.N, 64), (unsigned)cdiv(d.N, 4)),
-                           dim3(256), 0, s, d, r, v);
+        const float *rs = prescale2d(geom, r, s);
+        const dim3 grid((unsigned)cdiv(d.N, 8), (unsigned)cdiv(d.N, 8));
+        if (d.kind == INRCT_FAN2D)
+            hipLaunchKernelGGL(k_bproj2d<true>, grid, dim3(256), 0, s, d, rs, v);
+        else
+            hipLaunchKernelGGL(k_bproj2d<false>, grid, dim3(256), 0, s, d, rs, v);
         INRCT_CHECK_LAUNCH();
     } else {
         cone_backproject(geom, r, v, s);
@@ -334,8 +416,13 @@ void backproject_at(inrct_geom *geom, const float *r, const int32_t *idx, int64_
         return;
     }
     const GeomDev d = geom->dev();
-    hipLaunchKernelGGL(k_bproj_at, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, d, r,
-                       idx, k, out);
+    const float *rs = prescale2d(geom, r, s);
+    if (d.kind == INRCT_FAN2D)
+        hipLaunchKernelGGL(k_bproj_at<true>, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, d,
+                           rs, idx, k, out);
+    else
+        hipLaunchKernelGGL(k_bproj_at<false>, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, d,
+                           rs, idx, k, out);
     INRCT_CHECK_LAUNCH();
 }
 
@@ -401,11 +488,14 @@ int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, inrct_geom **o
             h->angles.assign(g->angles, g->angles + g->n_views);
             h->g.angles = h->angles.data();
             if (g->kind == INRCT_PAR2D || g->kind == INRCT_FAN2D) {
-                std::vector<ColGeom> cols;
-                std::vector<ViewGeom> views;
-                build_tables(h->g, h->N, cols, views);
+                std::vector<Col2D> cols;
+                std::vector<float> steps;
+                std::vector<View2D> views;
+                build_tables(h->g, h->N, cols, steps, views);
                 upload(h->cols, cols);
+                upload(h->steps, steps);
                 upload(h->views, views);
+                h->ut.alloc(sizeof(float) * (size_t)h->N * h->N);
             } else {
                 cone_build(h);
             }

@@ -85,7 +85,9 @@ def reservation_bytes(p: Problem, mlp_dtype: Optional[str] = None) -> int:
     k1 = p.arch.enc_dim
     es = 2 if dtype == "bf16" else 4
     vjp = P * (k1 + 2 * L * W + 1) * es + P * 64                          # activations, deltas, masks
-    part = -(-P // 2048) * 8 * (256 * 257) * 4                            # dW partials
+    ntiles = -(-k1 // 256) + L * -(-W // 256)                             # dW tiles
+    kslice = min(2048, max(512, -(-(-(-P // -(-256 // ntiles))) // 256) * 256))
+    part = -(-P // kslice) * ntiles * (256 * 257) * 4                      # dW partials
     frag = params * 2 * 4 * 2                                             # fragment streams
     flags = p.n_fov() + 4 * k
     return int(1.1 * (vol + rays + opt + vjp + part + frag + flags)) + (8 << 20)
