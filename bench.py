@@ -92,9 +92,9 @@ def cpu_baseline(p, target_s):
         pts = fov2[rng.choice(fov2.size, size=S)] + rng.integers(0, nz, S) * p.N * p.N
         X = ogrid.coords(p.dim, p.N, pts)
         t_e = timed(lambda: oinr.forward(theta, B, X, p.arch))
-        if t_e > budget / 2 or S >= 1 << 18:
+        if t_e > budget / 2 or S >= min(1 << 18, n):
             break
-        S *= 2
+        S = min(2 * S, n)
     per_E = t_e / S * n
     # P and P^T on R rays of view 0
     if p.dim == 3:

@@ -81,6 +81,8 @@ void cone_build(inrct_geom *hd) {
     // zero-bordered copies of u in both layouts ([z][y][x] and [z][x][y]);
     // the border is cleared once here and never written afterwards
     const size_t Np = (size_t)N + 2 * kPad;
+    // the projector addresses the padded copy with 32-bit element offsets
+    INRCT_REQUIRE(Np * Np * Np < ((size_t)1 << 31), "cone-beam grid n = %d exceeds 1286", N);
     hd->ut.alloc(sizeof(float) * Np * Np * Np * (any_x ? 2 : 1));
     INRCT_CHECK_HIP(hipMemset(hd->ut.ptr, 0, hd->ut.bytes));
     INRCT_CHECK_HIP(hipDeviceSynchronize());
@@ -189,10 +191,10 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
                                                   float *__restrict__ z, int ncx, int ncy) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb < 0) return;
-    // a wave is an 8 x 8 patch of rays (columns x rows); a block 16 x 16
+    // a wave is a 16 x 4 patch of rays (columns x rows); a block 16 x 16
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int a = (lb % ncx) * 16 + (wave & 1) * 8 + (lane & 7);
-    const int b = ((lb / ncx) % ncy) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int a = (lb % ncx) * 16 + (lane & 15);
+    const int b = ((lb / ncx) % ncy) * 16 + wave * 4 + (lane >> 4);
     const int j = lb / (ncx * ncy);
     if (a >= g.Nu || b >= g.Nv) return;
     const ConeCol c = g.col[(size_t)j * g.Nu + a];
