@@ -191,11 +191,16 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
                                                   float *__restrict__ z, int ncx, int ncy) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb < 0) return;
-    // a wave is a 16 x 4 patch of rays (columns x rows); a block 16 x 16
+    // a wave is a 16 x 4 patch of rays (columns x rows); a block 16 x 16.
+    // Blocks go in pairs of row tiles, column tiles next, then row-tile
+    // pairs, then views: both tiles that share a boundary row of voxels,
+    // and the tiles beside them, run at about the same time.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int a = (lb % ncx) * 16 + (lane & 15);
-    const int b = ((lb / ncx) % ncy) * 16 + wave * 4 + (lane >> 4);
-    const int j = lb / (ncx * ncy);
+    const int ngr = (ncy + 1) >> 1;
+    const int rt = ((lb / (2 * ncx)) % ngr) * 2 + (lb & 1);
+    const int a = ((lb >> 1) % ncx) * 16 + (lane & 15);
+    const int b = rt * 16 + wave * 4 + (lane >> 4);
+    const int j = lb / (2 * ncx * ngr);
     if (a >= g.Nu || b >= g.Nv) return;
     const ConeCol c = g.col[(size_t)j * g.Nu + a];
     const long long F0z = c.Z0 + (long long)b * c.Z1;
@@ -395,8 +400,9 @@ void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
                        dim3(256), 0, s, u, up, hd->any_x ? utp : nullptr, d.N);
     INRCT_CHECK_LAUNCH();
     const int ncx = (int)cdiv(d.Nu, 16), ncy = (int)cdiv(d.Nv, 16);
-    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ncy * d.V)), dim3(256), 0, s, d, up, utp, z,
-                       ncx, ncy);
+    const int ngr = (ncy + 1) / 2;  // row-tile pairs (the last may be half empty)
+    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ngr * 2 * d.V)), dim3(256), 0, s, d, up, utp,
+                       z, ncx, ncy);
     INRCT_CHECK_LAUNCH();
 }
 
