@@ -2,35 +2,51 @@
 product (Sec. III: grad L = sum_i v_i grad_theta f_theta(x_i); Eq. (2);
 Eq. (3)).
 
-Architectures (Sec. IV names FFN, SIREN and hash encoding; FFN and SIREN are
-built here):
+Architectures (Sec. IV names FFN, SIREN and hash encoding):
   * FFN (Fourier features + ReLU MLP): a_0 = [sin(2 pi B x); cos(2 pi B x)]
     (sin block first), z_l = W_l a_{l-1} + b_l, a_l = max(z_l, 0) for
     l = 1..L, f = w_out . a_L + b_out.  B is fixed (not trained).
   * SIREN: a_0 = x, a_l = sin(omega0 z_l) for l = 1..L, same linear output.
+  * hash encoding: a_0 = the multi-resolution hash encoding of x (module
+    ``hashenc``, whose tables are trained), then the FFN's ReLU MLP.
 
 Parameter vector layout: for each affine layer in order, W (fan_out x
-fan_in, row-major) then b; the output layer last.
+fan_in, row-major) then b; the output layer last.  The hash encoding's
+tables come before the MLP.
 
 The backward pass is textbook reverse mode (chain rule applied layer by
 layer), with ReLU'(0) taken as 0.
 """
 import numpy as np
 
+from . import hashenc
+
+
+def _enc_dim(arch):
+    if arch.kind == "ffn":
+        return 2 * arch.n_freq
+    if arch.kind == "hash":
+        return arch.hash_levels * arch.hash_feats
+    return arch.in_dim
+
+
+def _n_tab(arch):
+    return hashenc.n_table_params(arch) if arch.kind == "hash" else 0
+
 
 def layer_dims(arch):
-    enc = 2 * arch.n_freq if arch.kind == "ffn" else arch.in_dim
+    enc = _enc_dim(arch)
     dims = [(enc, arch.width)] + [(arch.width, arch.width)] * (arch.depth - 1)
     return dims + [(arch.width, 1)]
 
 
 def n_params(arch):
-    return sum(i * o + o for i, o in layer_dims(arch))
+    return _n_tab(arch) + sum(i * o + o for i, o in layer_dims(arch))
 
 
 def unpack(theta, arch):
     theta = np.asarray(theta, np.float64)
-    layers, off = [], 0
+    layers, off = [], _n_tab(arch)
     for fi, fo in layer_dims(arch):
         W = theta[off:off + fi * fo].reshape(fo, fi)
         off += fi * fo
@@ -47,8 +63,10 @@ def pack(grads):
     return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in grads])
 
 
-def encode(X, B, arch):
+def encode(X, B, arch, theta=None):
     X = np.asarray(X, np.float64)
+    if arch.kind == "hash":
+        return hashenc.encode(theta, X, arch)
     if arch.kind == "ffn":
         ph = 2.0 * np.pi * (X @ np.asarray(B, np.float64).T)
         return np.concatenate([np.sin(ph), np.cos(ph)], axis=1)
@@ -56,11 +74,11 @@ def encode(X, B, arch):
 
 
 def _act(z, arch):
-    return np.maximum(z, 0.0) if arch.kind == "ffn" else np.sin(arch.omega0 * z)
+    return np.maximum(z, 0.0) if arch.kind != "siren" else np.sin(arch.omega0 * z)
 
 
 def _act_grad(z, arch):
-    if arch.kind == "ffn":
+    if arch.kind != "siren":
         return (z > 0.0).astype(np.float64)
     return arch.omega0 * np.cos(arch.omega0 * z)
 
@@ -69,7 +87,7 @@ def forward(theta, B, X, arch, keep=False):
     """f_theta at the points X (k x d).  With keep=True also returns the
     layer inputs a_0..a_L and pre-activations z_1..z_L."""
     layers = unpack(theta, arch)
-    a = encode(X, B, arch)
+    a = encode(X, B, arch, theta)
     acts, pre = [a], []
     for W, b in layers[:-1]:
         z = a @ W.T + b
@@ -96,6 +114,9 @@ def vjp(theta, B, X, cot, arch):
         grads[l] = (g_z.T @ acts[l], g_z.sum(axis=0))
         if l > 0:
             g_a = g_z @ layers[l][0]                # dL/da_l
+    if arch.kind == "hash":                         # dL/da_0 into the tables
+        g_enc = g_z @ layers[0][0]
+        return np.concatenate([hashenc.encode_vjp(X, g_enc, arch), pack(grads)])
     return pack(grads)
 
 

@@ -30,17 +30,36 @@ from dataclasses import dataclass
 
 @dataclass(frozen=True)
 class INRArch:
-    kind: str            # "ffn" (Fourier features + ReLU MLP) or "siren"
+    kind: str            # "ffn" (Fourier features + ReLU MLP), "siren" or "hash"
     in_dim: int          # d = 2 or 3
     n_freq: int          # Fourier frequencies F (encoding width 2F); 0 for SIREN
     sigma: float         # std of the Gaussian Fourier matrix B
     width: int           # hidden width W
     depth: int           # number of hidden layers L
     omega0: float = 30.0 # SIREN frequency factor
+    # multi-resolution hash encoding (kind "hash"): levels, features per
+    # level, log2 of the entries per level's table, coarsest and finest
+    # resolution
+    hash_levels: int = 16
+    hash_feats: int = 2
+    hash_log2_size: int = 19
+    hash_base_res: int = 16
+    hash_max_res: int = 512
 
     @property
     def enc_dim(self) -> int:
-        return 2 * self.n_freq if self.kind == "ffn" else self.in_dim
+        if self.kind == "ffn":
+            return 2 * self.n_freq
+        if self.kind == "hash":
+            return self.hash_levels * self.hash_feats
+        return self.in_dim
+
+    @property
+    def n_table(self) -> int:
+        """Trained hash-table entries (floats) ahead of the MLP."""
+        if self.kind != "hash":
+            return 0
+        return self.hash_levels * (1 << self.hash_log2_size) * self.hash_feats
 
     def layer_dims(self):
         """(fan_in, fan_out) of each affine layer, output layer last."""
@@ -51,7 +70,7 @@ class INRArch:
 
     @property
     def n_params(self) -> int:
-        return sum(i * o + o for i, o in self.layer_dims())
+        return self.n_table + sum(i * o + o for i, o in self.layer_dims())
 
     def flops_forward(self) -> int:
         """Multiply-add FLOPs of one point's forward pass through the MLP."""

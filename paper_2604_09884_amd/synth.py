@@ -245,8 +245,10 @@ def init_inr(arch: INRArch, seed: int):
     others U(+-sqrt(6/fan_in)/omega0), zero biases."""
     rng = np.random.default_rng(seed)
     parts = []
+    if arch.kind == "hash":  # tables U(+-1e-4), as in the hash-encoding paper
+        parts.append(rng.uniform(-1e-4, 1e-4, size=arch.n_table))
     for li, (fi, fo) in enumerate(arch.layer_dims()):
-        if arch.kind == "ffn":
+        if arch.kind != "siren":
             lim = math.sqrt(6.0 / (fi + fo))
         else:
             lim = 1.0 / fi if li == 0 else math.sqrt(6.0 / fi) / arch.omega0
@@ -265,7 +267,9 @@ def random_theta(arch: INRArch, seed: int, bias_scale: float = 0.1):
     every bias gradient)."""
     theta, B = init_inr(arch, seed)
     rng = np.random.default_rng(seed + 7)
-    off = 0
+    if arch.kind == "hash":  # tables large enough to matter
+        theta[:arch.n_table] = rng.uniform(-0.5, 0.5, size=arch.n_table)
+    off = arch.n_table
     for fi, fo in arch.layer_dims():
         off += fi * fo
         theta[off:off + fo] = rng.uniform(-bias_scale, bias_scale, size=fo)
