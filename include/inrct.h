@@ -70,6 +70,7 @@ extern "C" {
 /* INR kinds and MLP precision */
 #define INRCT_FFN 1         /* Fourier features + ReLU MLP                 */
 #define INRCT_SIREN 2       /* sine-activated MLP                          */
+#define INRCT_HASH 3        /* multi-resolution hash encoding + ReLU MLP   */
 #define INRCT_FP32 0        /* FP32 matrix cores                           */
 #define INRCT_BF16 1        /* BF16 matrix cores, FP32 accumulation        */
 
@@ -104,14 +105,28 @@ typedef struct {
     const double *angles;   /* HOST array [n_views]                         */
 } ct_geometry;
 
+/* INR architectures (Sec. IV names all three).  HASH: the hash encoding of
+ * Mueller et al. (2022) with 2 features per level feeding a ReLU MLP.  Level
+ * l of Lh has resolution N_l = floor(base_res b^l + 1e-6), b = (max_res /
+ * base_res)^(1/(Lh-1)); a point x in [-1,1]^d lies at p = (x+1)/2 N_l; its
+ * cell's 2^d vertices c get multilinear weights; vertex c indexes the
+ * level's 2^log2_size-entry table densely (sum c_i (N_l+1)^i) when
+ * (N_l+1)^d fits, else by the spatial hash (XOR_i c_i pi_i) mod T, pi = (1,
+ * 2654435761, 805459861), 32-bit.  Parameters: the tables [Lh][T][2]
+ * first, then the MLP (input 2 Lh) in the usual layout.  HASH runs in FP32
+ * with width 16, 32 or 64 and width * depth <= 128. */
 typedef struct {
-    int kind;               /* INRCT_FFN or INRCT_SIREN                     */
+    int kind;               /* INRCT_FFN, INRCT_SIREN or INRCT_HASH         */
     int in_dim;             /* d = 2 or 3 (must equal the grid's dim)       */
     int n_freq;             /* FFN: F (encoding width 2F, F % 8 == 0)       */
-    int width;              /* hidden width: 128 or 256                     */
-    int depth;              /* hidden layers L (1..8)                       */
+    int width;              /* hidden width: 128 or 256 (HASH: 16, 32, 64)  */
+    int depth;              /* hidden layers L (1..8; HASH 1..4)            */
     float omega0;           /* SIREN frequency factor                       */
-    int mlp_dtype;          /* INRCT_FP32 or INRCT_BF16                     */
+    int mlp_dtype;          /* INRCT_FP32 or INRCT_BF16 (HASH: FP32)        */
+    int hash_levels;        /* HASH: Lh, 1..32                              */
+    int hash_log2_size;     /* HASH: log2 T, 4..24                          */
+    int hash_base_res;      /* HASH: N_0 >= 1                               */
+    int hash_max_res;       /* HASH: N_{Lh-1} >= N_0                        */
 } inr_arch;
 
 typedef struct inrct_geom inrct_geom;

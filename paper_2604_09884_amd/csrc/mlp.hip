@@ -1711,6 +1711,7 @@ static MlpDev make_dev(const inrct_model *m, const float *theta, const float *B)
 }
 
 void model_pack(inrct_model *m, const float *theta, hipStream_t s) {
+    if (m->arch.kind == INRCT_HASH) return;  // reads theta directly
     const MlpDev d = make_dev(m, theta, nullptr);
     const int slots = m->bf16() ? 8 : 1;
     const long long total = (m->nfrag + m->nfragT) * 64 * slots;
@@ -1792,6 +1793,10 @@ static void launch_eval_lds(const inrct_model *m, const MlpDev &d, float *u, hip
 
 void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u,
                     hipStream_t s) {
+    if (m->arch.kind == INRCT_HASH) {
+        hash_eval(m, theta, nullptr, m->n_fov, u, s);
+        return;
+    }
     const MlpDev d = make_dev(m, theta, B);
     const bool lds_path = m->bf16() &&
                           (m->arch.kind != INRCT_FFN ||
@@ -1831,6 +1836,10 @@ void model_eval_grid(inrct_model *m, const float *theta, const float *B, float *
 
 static void model_eval_points(inrct_model *m, const float *theta, const float *B,
                               const int32_t *idx, long long k, float *out, hipStream_t s) {
+    if (m->arch.kind == INRCT_HASH) {
+        hash_eval(m, theta, idx, k, out, s);
+        return;
+    }
     model_pack(m, theta, s);
     const MlpDev d = make_dev(m, theta, B);
     INRCT_DISPATCH_W_BF(m, launch_eval_points, d, idx, k, out, s);
@@ -1886,6 +1895,10 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
 void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t *idx,
                long long k, const float *v, int v_compact, double scale, float *grad,
                hipStream_t s, bool pack) {
+    if (m->arch.kind == INRCT_HASH) {
+        hash_vjp(m, theta, idx, k, v, v_compact, scale, grad, s);
+        return;
+    }
     if (pack) model_pack(m, theta, s);
     const MlpDev d = make_dev(m, theta, B);
     const long long P = m->P_alloc;
@@ -1921,9 +1934,26 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
         INRCT_REQUIRE(grid->dim == 2 || grid->dim == 3, "grid dim must be 2 or 3");
         INRCT_REQUIRE(grid->n >= 1 && grid->n <= 4096, "grid n must be in [1, 4096]");
         INRCT_REQUIRE(a.in_dim == grid->dim, "arch in_dim must equal the grid dim");
-        INRCT_REQUIRE(a.kind == INRCT_FFN || a.kind == INRCT_SIREN, "unknown INR kind %d", a.kind);
-        INRCT_REQUIRE(a.width == 128 || a.width == 256, "width must be 128 or 256");
-        INRCT_REQUIRE(a.depth >= 1 && a.depth <= kMaxDepth, "depth must be in [1, %d]", kMaxDepth);
+        INRCT_REQUIRE(a.kind == INRCT_FFN || a.kind == INRCT_SIREN || a.kind == INRCT_HASH,
+                      "unknown INR kind %d", a.kind);
+        if (a.kind == INRCT_HASH) {
+            INRCT_REQUIRE(a.width == 16 || a.width == 32 || a.width == 64,
+                          "hash INR width must be 16, 32 or 64");
+            INRCT_REQUIRE(a.depth >= 1 && a.depth <= kHashMaxDepth && a.width * a.depth <= 128,
+                          "hash INR needs 1 <= depth <= 4 and width * depth <= 128");
+            INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32, "hash INR runs in FP32");
+            INRCT_REQUIRE(a.hash_levels >= 1 && a.hash_levels <= kHashMaxLevels,
+                          "hash levels must be in [1, %d]", kHashMaxLevels);
+            INRCT_REQUIRE(a.hash_log2_size >= 4 && a.hash_log2_size <= 24,
+                          "hash table size must be 2^4 .. 2^24");
+            INRCT_REQUIRE(a.hash_base_res >= 1 && a.hash_max_res >= a.hash_base_res &&
+                              a.hash_max_res <= (1 << 20),
+                          "hash resolutions must satisfy 1 <= base <= max <= 2^20");
+        } else {
+            INRCT_REQUIRE(a.width == 128 || a.width == 256, "width must be 128 or 256");
+            INRCT_REQUIRE(a.depth >= 1 && a.depth <= kMaxDepth, "depth must be in [1, %d]",
+                          kMaxDepth);
+        }
         INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32 || a.mlp_dtype == INRCT_BF16, "unknown mlp dtype");
         if (a.kind == INRCT_FFN)
             INRCT_REQUIRE(a.n_freq >= 8 && a.n_freq % 8 == 0 && a.n_freq <= 4096,
@@ -1947,6 +1977,18 @@ int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k
             m->n_fov = m->fov.n;
             INRCT_REQUIRE(m->n_fov >= 1, "empty FOV");
             m->max_k = std::min<long long>(max_k, m->n_fov);
+            if (a.kind == INRCT_HASH) {
+                hash_setup(m);
+                // sampler scratch and Adam partials, as below
+                m->flags.alloc((size_t)m->n_fov);
+                m->n_blk = cdiv(m->n_fov, 4096);
+                m->blk.alloc((size_t)(m->n_blk + 1) * sizeof(int64_t));
+                m->n_apart = (int)std::min<long long>(
+                    1024, std::max<long long>(1, cdiv(m->n_params, 2048)));
+                m->apart.alloc(sizeof(double) * m->n_apart);
+                *out = m;
+                return;
+            }
             const int W = a.width, L = a.depth, d = a.in_dim;
             const bool bf = a.mlp_dtype == INRCT_BF16;
             const int kps = bf ? 16 : 2;

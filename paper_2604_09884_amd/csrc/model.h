@@ -3,6 +3,12 @@
 
 #include "geom.h"
 
+namespace inrct {
+constexpr int kHashMaxLevels = 32;  // hash encoding: levels per model
+constexpr int kHashMaxDepth = 4;    // hash encoding: hidden layers
+constexpr int kHashSlice = 2048;    // hash VJP: points per dW partial sum
+}  // namespace inrct
+
 struct inrct_model {
     inr_arch arch;
     int N = 0, dim = 0;
@@ -44,6 +50,14 @@ struct inrct_model {
     inrct::DevBuf apart;
     int n_apart = 0;
 
+    // hash encoding: level resolutions, per-point VJP rows, table-gradient
+    // contributions (keys, positions, sorted copies, values), sort scratch
+    // and dW slice partials
+    int hash_res[inrct::kHashMaxLevels] = {0};
+    int hash_row = 0, hash_key_bits = 0;
+    inrct::DevBuf hash_rows, hash_key, hash_pos, hash_skey, hash_spos, hash_val, hash_tmp,
+        hash_part;
+
     bool bf16() const { return arch.mlp_dtype == INRCT_BF16; }
 };
 
@@ -58,6 +72,12 @@ void model_eval_fov(inrct_model *m, const float *theta, const float *B, float *u
 void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t *idx,
                long long k, const float *v, int v_compact, double scale, float *grad,
                hipStream_t s, bool pack = true);
+// hash-encoding INR (hash.hip)
+void hash_setup(inrct_model *m);
+void hash_eval(inrct_model *m, const float *theta, const int32_t *idx, long long n,
+               float *out, hipStream_t s);
+void hash_vjp(inrct_model *m, const float *theta, const int32_t *idx, long long k,
+              const float *v, int v_compact, double scale, float *grad, hipStream_t s);
 void model_sample(inrct_model *m, uint64_t seed, uint64_t step, long long k, int32_t *idx,
                   hipStream_t s);
 void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float *g,

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libinrct.so")
 
 INRCT_OK = 0
 INRCT_PAR2D, INRCT_CONE3D, INRCT_FAN2D = 1, 2, 3
-INRCT_FFN, INRCT_SIREN = 1, 2
+INRCT_FFN, INRCT_SIREN, INRCT_HASH = 1, 2, 3
 INRCT_FP32, INRCT_BF16 = 0, 1
 INRCT_LS, INRCT_FLS = 0, 1
 INRCT_V_FULL, INRCT_V_AT_I = 0, 1
@@ -36,7 +36,9 @@ class CtGeometry(ctypes.Structure):
 
 class InrArch(ctypes.Structure):
     _fields_ = [("kind", c_int), ("in_dim", c_int), ("n_freq", c_int), ("width", c_int),
-                ("depth", c_int), ("omega0", c_float), ("mlp_dtype", c_int)]
+                ("depth", c_int), ("omega0", c_float), ("mlp_dtype", c_int),
+                ("hash_levels", c_int), ("hash_log2_size", c_int), ("hash_base_res", c_int),
+                ("hash_max_res", c_int)]
 
 
 class StepCfg(ctypes.Structure):

@@ -111,7 +111,13 @@ def residual_loss(geom: Geometry, z, y, loss=L.INRCT_LS, r=None):
 
 def arch_struct(arch: INRArch, mlp_dtype: str):
     a = L.InrArch()
-    a.kind = L.INRCT_FFN if arch.kind == "ffn" else L.INRCT_SIREN
+    kinds = {"ffn": L.INRCT_FFN, "siren": L.INRCT_SIREN, "hash": L.INRCT_HASH}
+    a.kind = kinds[arch.kind]
+    if arch.kind == "hash":
+        if arch.hash_feats != 2:
+            raise ValueError("the hash encoding runs with 2 features per level")
+        a.hash_levels, a.hash_log2_size = arch.hash_levels, arch.hash_log2_size
+        a.hash_base_res, a.hash_max_res = arch.hash_base_res, arch.hash_max_res
     a.in_dim, a.n_freq, a.width, a.depth = arch.in_dim, arch.n_freq, arch.width, arch.depth
     a.omega0 = arch.omega0
     a.mlp_dtype = L.INRCT_BF16 if mlp_dtype == "bf16" else L.INRCT_FP32

@@ -1,0 +1,97 @@
+"""GPU parity of the hash-encoding INR (E, the Eq. (2) VJP and a whole
+step) against the FP64 oracle, FP32 tolerances (1e-4 norm-wise)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grid as ogrid
+from oracle import inr as oinr
+from oracle import sampler as osampler
+from oracle import step as ostep
+from paper_2604_09884_amd import configs, synth
+from tests.gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _arch(d, W, L, levels, log2, base, top):
+    return configs.INRArch("hash", d, 0, 0.0, W, L, hash_levels=levels, hash_feats=2,
+                           hash_log2_size=log2, hash_base_res=base, hash_max_res=top)
+
+
+CASES = [
+    ("hash2d-w32", _arch(2, 32, 2, 8, 10, 4, 64), configs.fan2d_problem(45, 16, 67)),
+    ("hash3d-w16", _arch(3, 16, 3, 6, 12, 2, 24), configs.cone_problem(20, 6, 24)),
+    ("hash2d-w64", _arch(2, 64, 2, 12, 12, 8, 128), configs.par2d_problem(33, 12, 49)),
+]
+
+
+def _away_from_kinks(theta, arch, X, margin):
+    _, _, pre = oinr.forward(theta, None, X, arch, keep=True)
+    ok = np.ones(X.shape[0], bool)
+    for z in pre:
+        ok &= np.all(np.abs(z) > margin * np.sqrt(np.mean(z * z)), axis=1)
+    return ok
+
+
+@pytest.mark.parametrize("name,arch,prob", CASES, ids=[c[0] for c in CASES])
+def test_hash_eval_and_vjp_match_oracle(name, arch, prob):
+    from paper_2604_09884_amd import ops
+    say("case", name)
+    dim, N = prob.dim, prob.N
+    theta, _ = synth.random_theta(arch, 21)
+    fov = ogrid.fov_indices(dim, N)
+    m = ops.Model(arch, dim, N, "fp32", max_k=fov.size)
+    assert m.n_params == arch.n_params == theta.size
+    th, Bd = dev(theta), dev(np.zeros(1))
+    u = host(ops.inr_eval_grid(m, th, Bd)).ravel()
+    u_ref = oinr.eval_grid(theta, None, arch, dim, N, fov, ogrid.coords).ravel()
+    say(name, "E rel", rel(u, u_ref))
+    assert rel(u, u_ref) <= 1e-4
+    assert np.all(u[np.setdiff1d(np.arange(N ** dim), fov)] == 0)
+    # point evaluation at a ragged list
+    idx = np.sort(np.random.default_rng(22).choice(fov, size=fov.size // 3 + 7, replace=False))
+    f = host(ops.inr_eval_points(m, th, Bd, dev(idx, torch.int32)))
+    assert rel(f, u_ref[idx]) <= 1e-4
+    # Eq. (2) with the cotangent of Algorithm 1 on points away from ReLU kinks
+    op = ostep.Problem(prob.with_(arch=arch))
+    y = synth.sinogram(prob.with_(n_ellipses=4), noisy=False).ravel()
+    v_alg = op.P.T @ (op.P @ op.E(theta, None) - y)
+    keep = _away_from_kinks(theta, arch, ogrid.coords(dim, N, fov), 1e-4)
+    cand = fov[keep]
+    k = max(1, (cand.size * 2) // 3 - 5)
+    idx = np.sort(np.random.default_rng(23).choice(cand, size=k, replace=False))
+    scale = fov.size / k
+    g = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(v_alg), scale))
+    g_ref = oinr.vjp(theta, None, ogrid.coords(dim, N, idx), scale * v_alg[idx], arch)
+    nt = arch.n_table
+    say(name, "g rel", rel(g, g_ref), "tables", rel(g[:nt], g_ref[:nt]), "mlp",
+        rel(g[nt:], g_ref[nt:]))
+    assert rel(g, g_ref) <= 1e-4
+    assert rel(g[:nt], g_ref[:nt]) <= 1e-4 and rel(g[nt:], g_ref[nt:]) <= 1e-4
+    # entries no point touches are exactly zero, and the result repeats bitwise
+    assert np.all(g[:nt][g_ref[:nt] == 0] == 0)
+    g2 = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(v_alg), scale))
+    assert np.array_equal(g, g2)
+
+
+def test_hash_step_matches_oracle():
+    from paper_2604_09884_amd import ops
+    arch = _arch(2, 32, 2, 8, 10, 4, 64)
+    p = configs.fan2d_problem(40, 24, 57, arch=arch, k_frac=0.25, n_ellipses=5, lr=1e-3)
+    theta, _ = synth.init_inr(arch, p.seed_init)
+    y = synth.sinogram(p).astype(np.float32)
+    m = ops.Model(arch, 2, p.N, "fp32", max_k=p.k())
+    g = ops.Geometry(p)
+    st = ops.GradStepper(m, g, dev(theta), dev(np.zeros(1)), dev(y.ravel()), p.k(), p.lr,
+                         seed=p.seed_sampler)
+    prob = ostep.Problem(p)
+    st.step(2)
+    idx = osampler.sample_indices(prob.fov, st.k, p.seed_sampler, 2)
+    g_ref, L_ref, *_ = ostep.grad_estimate(prob, theta, None, y.reshape(-1).astype(np.float64),
+                                           idx)
+    gg = host(st.buffer(3, m.n_params))
+    say("hash step loss", float(host(st.loss)), L_ref, "g rel", rel(gg, g_ref))
+    assert abs(float(host(st.loss)) - L_ref) <= 1e-5 * L_ref
+    assert rel(gg, g_ref) <= 1e-4
+    st.close()
