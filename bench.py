@@ -274,10 +274,16 @@ def main():
         % (a.steps, ms_step, loss, {k_: round(v / a.steps, 3) for k_, v in stages.items()}))
 
     traffic = e_kernel_traffic() if a.config == "c4" and dtype == "bf16" else None
+    if p.arch.kind == "hash":
+        traffic = None
     flop_per_point = p.arch.flops_forward()
+    if p.arch.kind == "hash":  # plus the interpolation: 2^d weights x 2 features per level
+        flop_per_point += p.arch.hash_levels * (1 << p.dim) * 2 * 2
     e_ms = stages["eval_grid"] / a.steps
     achieved = model.n_fov * flop_per_point / (e_ms * 1e-3)
-    roofline = {"bound": "mfma", "kernel": "k_eval_lds_w (grid evaluation E)",
+    hashed = p.arch.kind == "hash"
+    roofline = {"bound": "alu" if hashed else "mfma",
+                "kernel": ("k_hash_eval" if hashed else "k_eval_lds_w") + " (grid evaluation E)",
                 "achieved": achieved / 1e12, "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[dtype], "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated; "

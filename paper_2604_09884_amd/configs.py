@@ -219,7 +219,16 @@ C6 = Problem(
     steps=5000, mlp_dtype="bf16",
     seed_phantom=1006, seed_noise=2006, seed_init=3006, seed_sampler=4006)
 
-CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c6": C6}
+# C6's fan-beam acquisition with the hash-encoding INR (the third
+# architecture of Sec. IV): 16 levels of 2^19 two-feature entries from
+# resolution 16 to 512, then 2 x 64 ReLU -> 1, FP32; |I| = n/16.
+C7 = C6.with_(name="fan2d-512-hash",
+              arch=INRArch("hash", 2, 0, 0.0, 64, 2, hash_levels=16, hash_feats=2,
+                           hash_log2_size=19, hash_base_res=16, hash_max_res=512),
+              mlp_dtype="fp32", seed_phantom=1007, seed_noise=2007, seed_init=3007,
+              seed_sampler=4007)
+
+CONFIGS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c6": C6, "c7": C7}
 
 
 # C5, the serving mix: request kinds uniform over {2D-256, 2D-512, 3D-128,

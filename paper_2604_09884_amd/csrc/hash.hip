@@ -48,7 +48,7 @@ __device__ __forceinline__ unsigned hash_index(const HashDev &h, int l, int cx, 
 }
 
 // The two interpolated features of level l at grid point (ix, iy, iz); if
-// W8 is given, also the cell's vertex indices and weights.
+// vidx is given, also the cell's vertex indices and weights (vw).
 __device__ __forceinline__ float2 hash_level(const HashDev &h, int l, int ix, int iy, int iz,
                                              unsigned *vidx, float *vw) {
     int cx, cy, cz = 0;
@@ -244,12 +244,21 @@ __global__ __launch_bounds__(256) void k_hash_dw(HashDev h, const float *__restr
         j = -1;  // bias
     }
     const long long p0 = (long long)s * S, p1 = min(k, p0 + S);
-    float acc = 0.f;
-    for (long long p = p0; p < p1; ++p) {
-        const float *row = rows + (size_t)p * R;
-        acc += j >= 0 ? row[dof + i] * row[aof + j] : row[dof + i];
+    // four interleaved partial sums (points p0 + 4q + r go to sum r), added
+    // in a fixed order at the end
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const float *dp = rows + (size_t)p0 * R + dof + i;
+    const float *ap = rows + (size_t)p0 * R + (j >= 0 ? aof + j : 0);
+    long long p = p0;
+    for (; p + 4 <= p1; p += 4, dp += 4 * (size_t)R, ap += 4 * (size_t)R) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float dv = dp[(size_t)r * R];
+            acc[r] += j >= 0 ? dv * ap[(size_t)r * R] : dv;
+        }
     }
-    part[(size_t)s * n_mlp + e] = acc;
+    for (int r = 0; p < p1; ++p, ++r, dp += R, ap += R) acc[r] += j >= 0 ? dp[0] * ap[0] : dp[0];
+    part[(size_t)s * n_mlp + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 __global__ __launch_bounds__(256) void k_hash_dw_sum(const float *__restrict__ part, int ns,

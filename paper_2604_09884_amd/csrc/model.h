@@ -6,7 +6,7 @@
 namespace inrct {
 constexpr int kHashMaxLevels = 32;  // hash encoding: levels per model
 constexpr int kHashMaxDepth = 4;    // hash encoding: hidden layers
-constexpr int kHashSlice = 2048;    // hash VJP: points per dW partial sum
+constexpr int kHashSlice = 256;     // hash VJP: points per dW partial sum
 }  // namespace inrct
 
 struct inrct_model {

@@ -95,3 +95,29 @@ def test_hash_step_matches_oracle():
     assert abs(float(host(st.loss)) - L_ref) <= 1e-5 * L_ref
     assert rel(gg, g_ref) <= 1e-4
     st.close()
+
+
+def test_hash_full_size_sampled():
+    # the 512^2 hash workload's model: E at sampled FOV points and the VJP
+    # of a sampled index set, against the oracle point by point
+    from paper_2604_09884_amd import ops
+    p = configs.C7
+    arch, N = p.arch, p.N
+    theta, _ = synth.random_theta(arch, 31)
+    fov = ogrid.fov_indices(2, N)
+    m = ops.Model(arch, 2, N, "fp32", max_k=p.k())
+    th, Bd = dev(theta), dev(np.zeros(1))
+    u = host(ops.inr_eval_grid(m, th, Bd)).ravel()
+    pts = np.unique(np.concatenate([fov[np.random.default_rng(32).choice(fov.size, 4000)],
+                                    [fov[0], fov[-1]]]))
+    e = rel(u[pts], oinr.forward(theta, None, ogrid.coords(2, N, pts), arch))
+    say("C7 E sampled rel", e)
+    assert e <= 1e-4
+    keep = _away_from_kinks(theta, arch, ogrid.coords(2, N, pts), 1e-4)
+    idx = pts[keep][:2000]
+    v = np.random.default_rng(33).standard_normal(idx.size)
+    g = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(v), 3.0,
+                                    v_compact=True))
+    g_ref = oinr.vjp(theta, None, ogrid.coords(2, N, idx), 3.0 * v, arch)
+    say("C7 g rel", rel(g, g_ref))
+    assert rel(g, g_ref) <= 1e-4
