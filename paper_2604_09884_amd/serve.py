@@ -90,6 +90,13 @@ def reservation_bytes(p: Problem, mlp_dtype: Optional[str] = None) -> int:
     part = -(-P // kslice) * ntiles * (256 * 257) * 4                      # dW partials
     frag = params * 2 * 4 * 2                                             # fragment streams
     flags = p.n_fov() + 4 * k
+    if p.arch.kind == "hash":  # point rows, sorted contributions, dW slice partials
+        R = k1 + 2 * L * W + 1
+        nc = k * p.arch.hash_levels * (1 << p.dim)
+        n_mlp = params - p.arch.n_table
+        vjp = 4 * k * R + 24 * nc + 8 * nc
+        part = 4 * -(-k // 256) * n_mlp
+        frag = 0
     return int(1.1 * (vol + rays + opt + vjp + part + frag + flags)) + (8 << 20)
 
 
