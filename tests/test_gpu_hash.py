@@ -121,3 +121,22 @@ def test_hash_full_size_sampled():
     g_ref = oinr.vjp(theta, None, ogrid.coords(2, N, idx), 3.0 * v, arch)
     say("C7 g rel", rel(g, g_ref))
     assert rel(g, g_ref) <= 1e-4
+
+
+def test_hash_single_point_and_all_hashed_levels():
+    # k = 1, and a 3D model whose every level is hashed (T = 2^6 < (N_0+1)^3)
+    from paper_2604_09884_amd import ops
+    arch = _arch(3, 16, 1, 3, 6, 4, 9)
+    N = 11
+    theta, _ = synth.random_theta(arch, 41)
+    fov = ogrid.fov_indices(3, N)
+    m = ops.Model(arch, 3, N, "fp32", max_k=5)
+    th, Bd = dev(theta), dev(np.zeros(1))
+    u = host(ops.inr_eval_grid(m, th, Bd)).ravel()
+    assert rel(u, oinr.eval_grid(theta, None, arch, 3, N, fov, ogrid.coords).ravel()) <= 1e-4
+    idx = fov[[fov.size // 2]]
+    g = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(np.array([0.7])), 2.0,
+                                    v_compact=True))
+    g_ref = oinr.vjp(theta, None, ogrid.coords(3, N, idx), np.array([1.4]), arch)
+    assert rel(g, g_ref) <= 1e-4
+    assert np.count_nonzero(g[:arch.n_table]) <= 3 * 8 * 2

@@ -75,3 +75,24 @@ def test_one_subset_is_the_plain_step_and_oversized_geometry_is_refused():
     with pytest.raises(Exception, match="rays"):
         a.step_views(3, big, dev(np.zeros(big.n_rays, np.float32)))
     one.close()
+
+
+def test_single_view_subsets_fan():
+    # S = V: every step sees one view
+    from paper_2604_09884_amd import ops
+    p = configs.fan2d_problem(24, 5, 33, arch=ARCH2, k_frac=0.5, n_ellipses=3)
+    st, B, y = _stepper(p, "ls")
+    os_ = ops.OrderedSubsets(st, p.n_views)
+    prob = ostep.Problem(p)
+    yv = y.reshape(-1).astype(np.float64)
+    for t in range(p.n_views + 1):
+        th = host(st.theta).astype(np.float64)
+        os_.step(t)
+        sub, rows = ostep.subset_problem(prob, ostep.subset_views(p.n_views, p.n_views,
+                                                                  t % p.n_views))
+        idx = osampler.sample_indices(prob.fov, st.k, p.seed_sampler, t)
+        g_ref, L_ref, *_ = ostep.grad_estimate(sub, th, B, yv[rows], idx)
+        assert abs(float(host(st.loss)) - L_ref) <= 1e-5 * abs(L_ref)
+        assert rel(host(st.buffer(3, st.model.n_params)), g_ref) <= 1e-4
+    os_.close()
+    st.close()
