@@ -26,6 +26,7 @@ namespace inrct {
 
 static const double kFix40 = 1099511627776.0;  // 2^40
 static const int kPad = 2;  // zero border of the padded volume copies
+static const unsigned kConeFwdLdsCap = 54 * 1024;  // occupancy cap of k_cone_fwd
 
 // ------------------------------------------------------------------ host
 void cone_build(inrct_geom *hd) {
@@ -401,8 +402,12 @@ void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
     INRCT_CHECK_LAUNCH();
     const int ncx = (int)cdiv(d.Nu, 16), ncy = (int)cdiv(d.Nv, 16);
     const int ngr = (ncy + 1) / 2;  // row-tile pairs (the last may be half empty)
-    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ngr * 2 * d.V)), dim3(256), 0, s, d, up, utp,
-                       z, ncx, ncy);
+    // The launch reserves 54 KB of LDS it does not use, so that at most two
+    // blocks share a CU: with fewer rays in flight per XCD, the voxel lines a
+    // block fetches are still in L2 when the neighbouring blocks read them
+    // (10.3 -> 8.9 ms at 501^3; four blocks per CU 9.7 ms, one 12.5 ms).
+    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ngr * 2 * d.V)), dim3(256),
+                       kConeFwdLdsCap, s, d, up, utp, z, ncx, ncy);
     INRCT_CHECK_LAUNCH();
 }
 
