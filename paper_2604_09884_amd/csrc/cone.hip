@@ -192,15 +192,15 @@ __global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__rest
                                                   float *__restrict__ z, int ncx, int ncy) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb < 0) return;
-    // a wave is a 16 x 4 patch of rays (columns x rows); a block 16 x 16.
+    // a wave is an 8 x 8 patch of rays (columns x rows); a block 16 x 16.
     // Blocks go in pairs of row tiles, column tiles next, then row-tile
     // pairs, then views: both tiles that share a boundary row of voxels,
     // and the tiles beside them, run at about the same time.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ngr = (ncy + 1) >> 1;
     const int rt = ((lb / (2 * ncx)) % ngr) * 2 + (lb & 1);
-    const int a = ((lb >> 1) % ncx) * 16 + (lane & 15);
-    const int b = rt * 16 + wave * 4 + (lane >> 4);
+    const int a = ((lb >> 1) % ncx) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int b = rt * 16 + (wave >> 1) * 8 + (lane >> 3);
     const int j = lb / (2 * ncx * ngr);
     if (a >= g.Nu || b >= g.Nv) return;
     const ConeCol c = g.col[(size_t)j * g.Nu + a];
@@ -405,7 +405,8 @@ void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
     // The launch reserves 54 KB of LDS it does not use, so that at most two
     // blocks share a CU: with fewer rays in flight per XCD, the voxel lines a
     // block fetches are still in L2 when the neighbouring blocks read them
-    // (10.3 -> 8.9 ms at 501^3; four blocks per CU 9.7 ms, one 12.5 ms).
+    // (10.3 -> 8.6 ms at 501^3; four blocks per CU 9.7 ms, three 9.3 ms, one
+    // 12.5 ms).
     hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ngr * 2 * d.V)), dim3(256),
                        kConeFwdLdsCap, s, d, up, utp, z, ncx, ncy);
     INRCT_CHECK_LAUNCH();
