@@ -205,8 +205,11 @@ __device__ __forceinline__ void cand_bins(const GeomDev &g, const View2D &vg, fl
     if (FAN) {
         const float D1x = p1x - vg.sx, D1y = p1y - vg.sy;
         const float D2x = p2x - vg.sx, D2y = p2y - vg.sy;
-        u1 = (vg.ax * D1y - vg.ay * D1x) / (vg.eux * D1y - vg.euy * D1x);
-        u2 = (vg.ax * D2y - vg.ay * D2x) / (vg.eux * D2y - vg.euy * D2x);
+        // hardware reciprocal (about 1 ulp): far inside the 0.01-bin margin
+        u1 = (vg.ax * D1y - vg.ay * D1x) *
+             __builtin_amdgcn_rcpf(vg.eux * D1y - vg.euy * D1x);
+        u2 = (vg.ax * D2y - vg.ay * D2x) *
+             __builtin_amdgcn_rcpf(vg.eux * D2y - vg.euy * D2x);
     } else {
         u1 = p1x * vg.eux + p1y * vg.euy;
         u2 = p2x * vg.eux + p2y * vg.euy;

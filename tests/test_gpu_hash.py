@@ -75,7 +75,8 @@ def test_hash_eval_and_vjp_match_oracle(name, arch, prob):
     assert np.array_equal(g, g2)
 
 
-def test_hash_step_matches_oracle():
+@pytest.mark.parametrize("v_mode", [0, 1], ids=["v_full", "v_at_I"])
+def test_hash_step_matches_oracle(v_mode):
     from paper_2604_09884_amd import ops
     arch = _arch(2, 32, 2, 8, 10, 4, 64)
     p = configs.fan2d_problem(40, 24, 57, arch=arch, k_frac=0.25, n_ellipses=5, lr=1e-3)
@@ -84,7 +85,7 @@ def test_hash_step_matches_oracle():
     m = ops.Model(arch, 2, p.N, "fp32", max_k=p.k())
     g = ops.Geometry(p)
     st = ops.GradStepper(m, g, dev(theta), dev(np.zeros(1)), dev(y.ravel()), p.k(), p.lr,
-                         seed=p.seed_sampler)
+                         seed=p.seed_sampler, v_mode=v_mode)
     prob = ostep.Problem(p)
     st.step(2)
     idx = osampler.sample_indices(prob.fov, st.k, p.seed_sampler, 2)
