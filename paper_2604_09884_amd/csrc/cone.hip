@@ -264,8 +264,8 @@ __global__ __launch_bounds__(256) void k_cone_prescale(ConeDev g, const float *_
     rs[i] = r[i] * cone_step(g, g.col[(size_t)j * g.Nu + a], b);
 }
 
-// Columns whose ray crosses the in-plane segment p1-p2 (central projection
-// of the end points, rounded outwards).  Computed in single precision and
+// Columns whose ray crosses the in-plane segment p1-p2: those at positions
+// between the central projections of its end points.  Computed in single precision and
 // widened by a margin far above its rounding error: the caller tests every
 // candidate exactly, so extra columns cost time but never change a sum.
 __device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, float p1x,
@@ -279,7 +279,8 @@ __device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, 
     const float u2 = (ax * D2y - ay * D2x) / (eux * D2y - euy * D2x);
     const float c = 0.5f * (float)(g.Nu - 1);
     const float a1 = u1 / (float)g.du + c, a2 = u2 / (float)g.du + c;
-    float l = floorf(fminf(a1, a2) - 0.01f), r = ceilf(fmaxf(a1, a2) + 0.01f);
+    // the columns inside [a1, a2], widened by the margin
+    float l = ceilf(fminf(a1, a2) - 0.01f), r = floorf(fmaxf(a1, a2) + 0.01f);
     l = fmaxf(l, 0.f);
     r = fminf(r, (float)(g.Nu - 1));
     *lo = (int)l;

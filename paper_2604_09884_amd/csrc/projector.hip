@@ -189,8 +189,9 @@ __global__ __launch_bounds__(256) void k_proj2d(GeomDev g, const float *__restri
 }
 
 // ------------------------------------------------ adjoint (gather) helpers
-// Bins whose ray crosses the in-plane segment p1-p2, in single precision
-// and widened by 0.01 bin, far above its rounding error: every candidate is
+// Bins whose ray crosses the in-plane segment p1-p2 (the bins at positions
+// inside the segment's image on the detector), in single precision and
+// widened by 0.01 bin, far above its rounding error: every candidate is
 // then tested exactly on the fixed-point stencil, so an extra candidate
 // costs time but never changes a sum.  Parallel beam: the segment's
 // projection on the detector axis.  Fan beam: the central projection of its
@@ -216,7 +217,8 @@ __device__ __forceinline__ void cand_bins(const GeomDev &g, const View2D &vg, fl
     }
     const float c = 0.5f * (float)(g.Nu - 1);
     const float a1 = u1 * inv_du + c, a2 = u2 * inv_du + c;
-    float l = floorf(fminf(a1, a2) - 0.01f), r = ceilf(fmaxf(a1, a2) + 0.01f);
+    // the bins inside [a1, a2], widened by the margin
+    float l = ceilf(fminf(a1, a2) - 0.01f), r = floorf(fmaxf(a1, a2) + 0.01f);
     l = fmaxf(l, 0.f);
     r = fminf(r, (float)(g.Nu - 1));
     *lo = (int)l;
