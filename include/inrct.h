@@ -40,7 +40,8 @@
  *  - INR parameters theta: for each affine layer in order, W (fan_out x
  *    fan_in, row-major) then b, output layer last.  FFN layer 1 reads the
  *    encoding [sin(2 pi B x); cos(2 pi B x)] (sin block first); B is
- *    float32 [F][d], not trained.
+ *    float32 [F][d], not trained.  HASH: the encoding's tables [Lh][T][2]
+ *    come first (they are trained), then the MLP.
  *  - index sets: int32 grid linear indices, distinct, inside the FOV,
  *    ascending.
  */
