@@ -71,13 +71,28 @@ __global__ void k_mark(PrpKey key, long long k, unsigned char *__restrict__ flag
 }
 
 // per-block counts of set flags (4096 flags per block, 256 threads x 16)
+// Flags set among ranks [base, base + 16): one 16-byte load when the run
+// lies inside [0, n) (base is a multiple of 16, the array 256-byte
+// aligned), else byte by byte.
+__device__ __forceinline__ int count16(const unsigned char *__restrict__ flags, long long base,
+                                       long long n) {
+    if (base + 16 <= n) {
+        const uint4 w = *(const uint4 *)(flags + base);
+        // each byte is 0 or 1: the byte sum of a word is its count
+        auto bytes = [](unsigned x) { return (int)((x * 0x01010101u) >> 24); };
+        return bytes(w.x) + bytes(w.y) + bytes(w.z) + bytes(w.w);
+    }
+    int c = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < n) c += flags[base + i];
+    return c;
+}
+
 __global__ __launch_bounds__(256) void k_count(const unsigned char *__restrict__ flags,
                                                long long n, long long *__restrict__ blk) {
     __shared__ int sh[256];
     const long long base = (long long)blockIdx.x * 4096 + threadIdx.x * 16;
-    int c = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < n) c += flags[base + i];
+    const int c = count16(flags, base, n);
     sh[threadIdx.x] = c;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -116,9 +131,7 @@ __global__ __launch_bounds__(256) void k_emit(const unsigned char *__restrict__ 
                                               int32_t *__restrict__ out) {
     __shared__ int sh[256];
     const long long base = (long long)blockIdx.x * 4096 + threadIdx.x * 16;
-    int c = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < n) c += flags[base + i];
+    const int c = count16(flags, base, n);
     sh[threadIdx.x] = c;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
@@ -128,12 +141,32 @@ __global__ __launch_bounds__(256) void k_emit(const unsigned char *__restrict__ 
         __syncthreads();
     }
     long long pos = blk[blockIdx.x] + sh[threadIdx.x] - c;
+    if (c == 0) return;
+    // the row of the first set rank by binary search, later ones by walking
+    // forward (16 consecutive ranks cross at most a few row starts)
+    bool found = false;
+    int z = 0, y = 0;
+    long long zbase = 0;
     for (int i = 0; i < 16; ++i) {
         const long long q = base + i;
-        if (q < n && flags[q]) {
-            int x, y, z;
+        if (q >= n || !flags[q]) continue;
+        if (!found) {
+            int x;
             out[pos++] = (int32_t)fov_rank_to_index(fov, q, &x, &y, &z);
+            zbase = (long long)z * fov.n_slice;
+            found = true;
+            continue;
         }
+        long long rem = q - zbase;
+        while (rem >= fov.n_slice) {  // next z slice
+            ++z;
+            zbase += fov.n_slice;
+            rem -= fov.n_slice;
+            y = 0;
+        }
+        while (y + 1 < fov.N && fov.row_start[y + 1] <= rem) ++y;
+        const int x = fov.xlo[y] + (int)(rem - fov.row_start[y]);
+        out[pos++] = (int32_t)(((long long)z * fov.N + y) * fov.N + x);
     }
 }
 
