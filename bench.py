@@ -47,6 +47,10 @@ def parse():
                     help="measure serving instead: R requests of the C5 mix stepped together "
                          "versus one at a time (prints its own JSON line)")
     ap.add_argument("--serve-steps", type=int, default=4)
+    ap.add_argument("--serve-compare", action="store_true",
+                    help="with --serve: the mix in BF16 served together against the same "
+                         "mix in FP32 one request at a time, with each request's final image "
+                         "MSE in both forms")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy before the steps (a "
                          "reference for hardware byte counters)")
@@ -214,6 +218,84 @@ def serve_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def _fov_mask(dim, N):
+    c = -1.0 + (np.arange(N) + 0.5) * (2.0 / N)
+    disc = (c[None, :] ** 2 + c[:, None] ** 2) <= 1.0
+    return disc if dim == 2 else np.broadcast_to(disc, (N, N, N))
+
+
+def serve_compare(a):
+    """The C5 mix in two forms: every request in FP32, one at a time, and
+    every request in BF16, served together; throughput of each and every
+    request's final image MSE (over the FOV, against the rasterised
+    phantom) in both."""
+    import torch
+
+    from paper_2604_09884_amd import configs, ops, synth
+    from paper_2604_09884_amd.serve import DONE, Request, Server
+
+    torch.cuda.set_device(0)
+    probs = configs.serving_mix(a.serve, steps=a.serve_steps)
+    ys = [synth.sinogram(p).astype(np.float32) for p in probs]
+    log("C5 mix for the comparison: %s" % [p.name for p in probs])
+
+    def final_mse(p, theta):
+        m = ops.Model(p.arch, p.dim, p.N, "fp32", max_k=1)
+        th = torch.tensor(theta, dtype=torch.float32, device="cuda")
+        _, B = synth.init_inr(p.arch, p.seed_init)
+        Bd = torch.tensor(B.ravel() if B.size else np.zeros(1), dtype=torch.float32,
+                          device="cuda")
+        u = ops.inr_eval_grid(m, th, Bd).cpu().numpy().reshape([p.N] * p.dim)
+        ref = synth.raster(synth.phantom(p), p.dim, p.N)
+        msk = _fov_mask(p.dim, p.N)
+        m.close()
+        return float(np.mean((u[msk] - ref[msk]) ** 2))
+
+    # warm-up, both precisions
+    for dt in ("fp32", "bf16"):
+        srv = Server(n_streams=1)
+        srv.submit(Request(problem=probs[0], y=ys[0], steps=1, mlp_dtype=dt))
+        srv.run()
+    torch.cuda.synchronize()
+    t_a, mse_a = 0.0, []
+    for p, y in zip(probs, ys):
+        srv = Server(n_streams=1)
+        rid = srv.submit(Request(problem=p, y=y, steps=p.steps, mlp_dtype="fp32"))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        srv.run()
+        t_a += time.perf_counter() - t
+        assert srv.status(rid).state == DONE, srv.status(rid).error
+        mse_a.append(final_mse(p, srv.status(rid).theta))
+        log("FP32 alone: %s final MSE %.4g" % (p.name, mse_a[-1]))
+    srv = Server(n_streams=4)
+    ids = [srv.submit(Request(problem=p, y=y, steps=p.steps, mlp_dtype="bf16"))
+           for p, y in zip(probs, ys)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    srv.run()
+    t_b = time.perf_counter() - t
+    m = srv.metrics()
+    mse_b = []
+    for p, i in zip(probs, ids):
+        assert srv.status(i).state == DONE, srv.status(i).error
+        mse_b.append(final_mse(p, srv.status(i).theta))
+        log("BF16 served: %s final MSE %.4g" % (p.name, mse_b[-1]))
+    steps = sum(p.steps for p in probs)
+    rel = [abs(b - f) / f for f, b in zip(mse_a, mse_b)]
+    out = {
+        "metric": "served BF16 vs one-at-a-time FP32 grad steps/s (C5 serving mix)",
+        "value": steps / t_b, "unit": "steps/s", "n_gpus": 1, "requests": len(probs),
+        "steps_per_request": a.serve_steps, "fp32_one_at_a_time_steps_per_s": steps / t_a,
+        "speedup": t_a / t_b, "tick_ms_p50": m["tick_ms_p50"], "tick_ms_p99": m["tick_ms_p99"],
+        "final_mse_fp32_alone": mse_a, "final_mse_bf16_served": mse_b,
+        "max_rel_mse_difference": max(rel), "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": "C5 serving mix (seed 5005)",
+                   "requests": [p.name + ":" + p.arch.kind for p in probs]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -221,7 +303,10 @@ def main():
               "(requested --gpus %d)" % a.gpus, flush=True)
         sys.exit(2)
     if a.serve:
-        serve_bench(a)
+        if a.serve_compare:
+            serve_compare(a)
+        else:
+            serve_bench(a)
         return
     import torch
 
