@@ -49,26 +49,34 @@ __device__ __forceinline__ unsigned hash_index(const HashDev &h, int l, int cx, 
 
 // The two interpolated features of level l at grid point (ix, iy, iz); if
 // vidx is given, also the cell's vertex indices and weights (vw).
+// The 2^DIM table reads are issued together, then combined in vertex order.
+template <int DIM>
 __device__ __forceinline__ float2 hash_level(const HashDev &h, int l, int ix, int iy, int iz,
                                              unsigned *vidx, float *vw) {
+    constexpr int NV = 1 << DIM;
     int cx, cy, cz = 0;
     float fx, fy, fz = 0.f;
     hash_axis(ix, h.N, h.res[l], &cx, &fx);
     hash_axis(iy, h.N, h.res[l], &cy, &fy);
-    if (h.dim == 3) hash_axis(iz, h.N, h.res[l], &cz, &fz);
+    if (DIM == 3) hash_axis(iz, h.N, h.res[l], &cz, &fz);
     const float2 *tab = (const float2 *)(h.theta + (size_t)l * h.T * 2);
+    unsigned id[NV];
+    float2 t[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        id[m] = hash_index(h, l, cx + (m & 1), cy + ((m >> 1) & 1), cz + ((m >> 2) & 1));
+        t[m] = tab[id[m]];
+    }
     float2 e = make_float2(0.f, 0.f);
-    const int nv = h.dim == 3 ? 8 : 4;
-    for (int m = 0; m < nv; ++m) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
         const int bx = m & 1, by = (m >> 1) & 1, bz = (m >> 2) & 1;
         const float w = (bx ? fx : 1.f - fx) * (by ? fy : 1.f - fy) *
-                        (h.dim == 3 ? (bz ? fz : 1.f - fz) : 1.f);
-        const unsigned id = hash_index(h, l, cx + bx, cy + by, cz + bz);
-        const float2 t = tab[id];
-        e.x += w * t.x;
-        e.y += w * t.y;
+                        (DIM == 3 ? (bz ? fz : 1.f - fz) : 1.f);
+        e.x += w * t[m].x;
+        e.y += w * t[m].y;
         if (vidx) {
-            vidx[m] = id;
+            vidx[m] = id[m];
             vw[m] = w;
         }
     }
@@ -91,7 +99,7 @@ __device__ __forceinline__ void hash_point(const HashDev &h, long long q, int mo
 
 // Forward to the last hidden layer; acts[l] = a_{l+1}.  If enc is given,
 // the encoding a_0 is written there (K floats).
-template <int W, int LMAX>
+template <int W, int LMAX, int DIM>
 __device__ __forceinline__ void hash_forward(const HashDev &h, int ix, int iy, int iz,
                                              float (&acts)[LMAX][W], float *enc) {
     const float *W1 = h.theta + h.loff[1];
@@ -99,7 +107,7 @@ __device__ __forceinline__ void hash_forward(const HashDev &h, int ix, int iy, i
 #pragma unroll
     for (int i = 0; i < W; ++i) z[i] = W1[(size_t)W * h.K + i];
     for (int l = 0; l < h.levels; ++l) {
-        const float2 e = hash_level(h, l, ix, iy, iz, nullptr, nullptr);
+        const float2 e = hash_level<DIM>(h, l, ix, iy, iz, nullptr, nullptr);
         if (enc) {
             enc[2 * l] = e.x;
             enc[2 * l + 1] = e.y;
@@ -124,7 +132,7 @@ __device__ __forceinline__ void hash_forward(const HashDev &h, int ix, int iy, i
     }
 }
 
-template <int W, int LMAX>
+template <int W, int LMAX, int DIM>
 __global__ __launch_bounds__(256) void k_hash_eval(HashDev h, long long n, int mode,
                                                    const int32_t *__restrict__ idx,
                                                    float *__restrict__ out) {
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(256) void k_hash_eval(HashDev h, long long n, int m
     long long g;
     hash_point(h, q, mode, idx, &ix, &iy, &iz, &g);
     float acts[LMAX][W];
-    hash_forward<W, LMAX>(h, ix, iy, iz, acts, nullptr);
+    hash_forward<W, LMAX, DIM>(h, ix, iy, iz, acts, nullptr);
     const float *Wo = h.theta + h.loff[h.L + 1];
     float f = Wo[W];
     for (int l = 0; l < LMAX; ++l)
@@ -148,7 +156,7 @@ __global__ __launch_bounds__(256) void k_hash_eval(HashDev h, long long n, int m
 // Row of point t (R floats): a_0 (K) | a_1..a_L (W each) | d_1..d_L (W each)
 // | d_out.  Contributions of point t: (level, vertex) keys and the two
 // weighted feature gradients.
-template <int W, int LMAX>
+template <int W, int LMAX, int DIM>
 __global__ __launch_bounds__(256) void k_hash_vjp(HashDev h, const int32_t *__restrict__ idx,
                                                   long long k, const float *__restrict__ v,
                                                   int v_compact, float scale,
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(256) void k_hash_vjp(HashDev h, const int32_t *__re
     hash_point(h, t, 1, idx, &ix, &iy, &iz, &g);
     float *row = rows + (size_t)t * R;
     float acts[LMAX][W];
-    hash_forward<W, LMAX>(h, ix, iy, iz, acts, row);
+    hash_forward<W, LMAX, DIM>(h, ix, iy, iz, acts, row);
     const int K = h.K, L = h.L;
 #pragma unroll
     for (int l = 0; l < LMAX; ++l)
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(256) void k_hash_vjp(HashDev h, const int32_t *__re
     }
     // dL/da_0 and the table contributions, level by level
     const float *W1 = h.theta + h.loff[1];
-    const int nv = h.dim == 3 ? 8 : 4;
+    constexpr int nv = 1 << DIM;
     for (int l = 0; l < h.levels; ++l) {
         float d0 = 0.f, d1 = 0.f;
 #pragma unroll
@@ -209,8 +217,9 @@ __global__ __launch_bounds__(256) void k_hash_vjp(HashDev h, const int32_t *__re
         }
         unsigned vid[8];
         float vw[8];
-        (void)hash_level(h, l, ix, iy, iz, vid, vw);
+        (void)hash_level<DIM>(h, l, ix, iy, iz, vid, vw);
         const size_t base = ((size_t)t * h.levels + l) * nv;
+#pragma unroll
         for (int m = 0; m < nv; ++m) {
             ckey[base + m] = (uint32_t)l * (uint32_t)h.T + vid[m];
             cpos[base + m] = (uint32_t)(base + m);
@@ -318,17 +327,22 @@ static HashDev hash_dev(const inrct_model *m, const float *theta) {
     return h;
 }
 
-#define HASH_DISPATCH(W_, FN, ...)                                                   \
+#define HASH_DISPATCH_D(W_, D_, FN, ...)                                            \
     do {                                                                            \
-        if ((W_) == 16) FN<16, 4>(__VA_ARGS__);                                     \
-        else if ((W_) == 32) FN<32, 4>(__VA_ARGS__);                                \
-        else FN<64, 2>(__VA_ARGS__);                                                \
+        if ((W_) == 16) FN<16, 4, D_>(__VA_ARGS__);                                 \
+        else if ((W_) == 32) FN<32, 4, D_>(__VA_ARGS__);                            \
+        else FN<64, 2, D_>(__VA_ARGS__);                                            \
+    } while (0)
+#define HASH_DISPATCH(W_, DIM_, FN, ...)                                             \
+    do {                                                                            \
+        if ((DIM_) == 3) HASH_DISPATCH_D(W_, 3, FN, __VA_ARGS__);                   \
+        else HASH_DISPATCH_D(W_, 2, FN, __VA_ARGS__);                               \
     } while (0)
 
-template <int W, int LM>
+template <int W, int LM, int DIM>
 static void launch_hash_eval(const HashDev &h, long long n, int mode, const int32_t *idx,
                              float *out, hipStream_t s) {
-    hipLaunchKernelGGL((k_hash_eval<W, LM>), dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, h,
+    hipLaunchKernelGGL((k_hash_eval<W, LM, DIM>), dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, h,
                        n, mode, idx, out);
 }
 
@@ -336,15 +350,15 @@ void hash_eval(inrct_model *m, const float *theta, const int32_t *idx, long long
                float *out, hipStream_t s) {
     if (n <= 0) return;
     const HashDev h = hash_dev(m, theta);
-    HASH_DISPATCH(h.W, launch_hash_eval, h, n, idx ? 1 : 0, idx, out, s);
+    HASH_DISPATCH(h.W, h.dim, launch_hash_eval, h, n, idx ? 1 : 0, idx, out, s);
     INRCT_CHECK_LAUNCH();
 }
 
-template <int W, int LM>
+template <int W, int LM, int DIM>
 static void launch_hash_vjp(const HashDev &h, const int32_t *idx, long long k, const float *v,
                             int v_compact, float scale, float *rows, int R, uint32_t *ckey,
                             uint32_t *cpos, float2 *cval, hipStream_t s) {
-    hipLaunchKernelGGL((k_hash_vjp<W, LM>), dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, h,
+    hipLaunchKernelGGL((k_hash_vjp<W, LM, DIM>), dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, h,
                        idx, k, v, v_compact, scale, rows, R, ckey, cpos, cval);
 }
 
@@ -369,8 +383,8 @@ void hash_vjp(inrct_model *m, const float *theta, const int32_t *idx, long long 
     uint32_t *skey = m->hash_skey.as<uint32_t>(), *spos = m->hash_spos.as<uint32_t>();
     float2 *cval = m->hash_val.as<float2>();
     float *rows = m->hash_rows.as<float>();
-    HASH_DISPATCH(h.W, launch_hash_vjp, h, idx, k, v, v_compact, (float)scale, rows, R, ckey,
-                  cpos, cval, s);
+    HASH_DISPATCH(h.W, h.dim, launch_hash_vjp, h, idx, k, v, v_compact, (float)scale, rows, R,
+                  ckey, cpos, cval, s);
     INRCT_CHECK_LAUNCH();
     // MLP weight gradients: slices of kHashSlice points, then their sum
     const int ns = (int)cdiv(k, kHashSlice);
