@@ -295,11 +295,25 @@ __global__ __launch_bounds__(256) void k_hash_runs(const uint32_t *__restrict__ 
     if (s >= n) return;
     const uint32_t kk = key[s];
     if (s > 0 && key[s - 1] == kk) return;
+    // eight sorted entries per iteration, their loads issued together; keys
+    // are ascending, so the run ends at the first different key
     float gx = 0.f, gy = 0.f;
-    for (long long q = s; q < n && key[q] == kk; ++q) {
-        const float2 c = val[pos[q]];
-        gx += c.x;
-        gy += c.y;
+    for (long long q = s; q < n; q += 8) {
+        uint32_t kq[8], pq[8];
+        float2 vq[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) kq[i] = q + i < n ? key[q + i] : kk + 1u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pq[i] = kq[i] == kk ? pos[q + i] : 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vq[i] = kq[i] == kk ? val[pq[i]] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (kq[i] == kk) {
+                gx += vq[i].x;
+                gy += vq[i].y;
+            }
+        if (kq[7] != kk) break;
     }
     grad[2 * (size_t)kk] = gx;
     grad[2 * (size_t)kk + 1] = gy;
