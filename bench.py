@@ -353,6 +353,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     stages = st.stage_ms()
+    free2, _ = torch.cuda.mem_get_info()
     ms_step = wall * 1e3 / a.steps
     loss = float(st.loss)
     log("timed %d steps: %.2f ms/step, loss %.6g, stages %s"
@@ -399,6 +400,9 @@ def main():
                    "v_mode": a.v_mode, "subsets": a.subsets, "parallelism": "single GPU"},
         "stages_ms_per_step": {k_: v / a.steps for k_, v in stages.items()},
         "device_mem_gb": (free0 - free1) / 1e9,
+        # the library allocates only when handles are created, so the
+        # footprint after the timed steps is the peak of the whole run
+        "peak_device_mem_gb": (free0 - min(free1, free2)) / 1e9,
         "loss_last": loss,
         "roofline": roofline,
     }
