@@ -40,3 +40,26 @@ def test_errors_are_reported_without_a_gpu():
     rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
     assert rc == -1
     assert b"grid n" in lib.inrct_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stdout
+
+
+def test_hash_arch_is_checked_before_any_device_call():
+    lib = L.load()
+    h = ctypes.c_void_p()
+    grid = L.InrGrid(2, 16)
+    # width 128 is not a hash-INR width
+    a = L.InrArch(L.INRCT_HASH, 2, 0, 128, 2, 30.0, L.INRCT_FP32, 4, 10, 4, 16)
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
+    assert rc != 0 and b"width" in lib.inrct_last_error()
+    # BF16 is refused for the hash INR
+    a = L.InrArch(L.INRCT_HASH, 2, 0, 64, 2, 30.0, L.INRCT_BF16, 4, 10, 4, 16)
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
+    assert rc != 0 and b"FP32" in lib.inrct_last_error()
