@@ -63,3 +63,23 @@ def test_hash_arch_is_checked_before_any_device_call():
     a = L.InrArch(L.INRCT_HASH, 2, 0, 64, 2, 30.0, L.INRCT_BF16, 4, 10, 4, 16)
     rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
     assert rc != 0 and b"FP32" in lib.inrct_last_error()
+
+
+def test_fan_geometry_checks_on_the_host():
+    lib = L.load()
+    angles = (ctypes.c_double * 4)(0.0, 0.5, 1.0, 1.5)
+    grid = L.InrGrid(2, 32)
+    h = ctypes.c_void_p()
+
+    def make(n_u, du, sid, idd, n_v=1):
+        g = L.CtGeometry()
+        g.kind, g.n_views, g.n_u, g.n_v = L.INRCT_FAN2D, 4, n_u, n_v
+        g.du, g.dv, g.sid, g.idd = du, du, sid, idd
+        g.angles = ctypes.cast(angles, ctypes.POINTER(ctypes.c_double))
+        return lib.inrct_geom_create(ctypes.byref(g), ctypes.byref(grid), ctypes.byref(h))
+
+    assert make(64, 0.05, 1.2, 1.0) != 0          # source inside the image
+    assert b"outside" in lib.inrct_last_error()
+    assert make(64, 0.05, 3.0, 1.0, n_v=2) != 0   # a fan has one detector row
+    assert make(101, 1.0, 3.0, 1.0) != 0          # a fan wider than 90 degrees
+    assert b"90" in lib.inrct_last_error()
