@@ -359,6 +359,30 @@ def main():
     log("timed %d steps: %.2f ms/step, loss %.6g, stages %s"
         % (a.steps, ms_step, loss, {k_: round(v / a.steps, 3) for k_, v in stages.items()}))
 
+    # the same steps with v formed only at the sampled points (the entries
+    # Eq. (2) consumes; the same g up to summation order), from the same
+    # starting parameters, reported beside the literal full-grid v
+    alt = None
+    if a.v_mode == "full" and a.subsets == 1:
+        th2 = torch.tensor(theta, dtype=torch.float32, device=dev)
+        st2 = ops.GradStepper(model, geom, th2, Bd, yd, k, p.lr, seed=p.seed_sampler,
+                              v_mode=L.INRCT_V_AT_I)
+        for t in range(a.warmup):
+            st2.step(t)
+        st2.enable_timing(max(1, a.steps))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for t in range(a.steps):
+            st2.step(a.warmup + t)
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t2) * 1e3 / a.steps
+        st2_stages = st2.stage_ms()
+        alt = {"v_mode": "at_i", "value": 1e3 / ms2, "ms_per_step": ms2,
+               "backproject_ms": st2_stages["backproject"] / a.steps,
+               "loss_last": float(st2.loss)}
+        log("v at I: %.2f ms/step (P^T at I %.3f ms)" % (ms2, alt["backproject_ms"]))
+        st2.close()
+
     traffic = e_kernel_traffic() if a.config == "c4" and dtype == "bf16" else None
     if p.arch.kind == "hash":
         traffic = None
@@ -406,6 +430,8 @@ def main():
         "loss_last": loss,
         "roofline": roofline,
     }
+    if alt is not None:
+        out["v_at_I"] = alt
     if not a.no_cpu:
         log("timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
