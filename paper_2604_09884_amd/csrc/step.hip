@@ -301,6 +301,9 @@ int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *c
             c->B = B;
             c->y = y;
             c->u.alloc(sizeof(float) * model->n_grid);
+            // u outside the FOV is 0 and no step writes there: cleared once
+            INRCT_CHECK_HIP(hipMemset(c->u.ptr, 0, c->u.bytes));
+            INRCT_CHECK_HIP(hipDeviceSynchronize());
             c->m_cap = geom_rays(geom);
             c->r.alloc(sizeof(float) * c->m_cap);
             c->v.alloc(sizeof(float) * (cfg->v_mode == INRCT_V_FULL ? model->n_grid : cfg->k));
@@ -381,7 +384,6 @@ static void grad_step(inr_ctx *c, uint64_t step, inrct_geom *geom, const float *
     mark(7, 0);
     // Algorithm 1, step 1: z = P E{f_theta}
     model_pack(m, c->theta, s);
-    model_zero_outside(m, u, s);
     mark(0, 0);
     model_eval_fov(m, c->theta, c->B, u, s);
     mark(0, 1);
