@@ -44,13 +44,15 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve", type=int, default=0, metavar="R",
-                    help="measure serving instead: R requests of the C5 mix stepped together "
-                         "versus one at a time (prints its own JSON line)")
-    ap.add_argument("--serve-steps", type=int, default=4)
-    ap.add_argument("--serve-compare", action="store_true",
-                    help="with --serve: the mix in BF16 served together against the same "
-                         "mix in FP32 one request at a time, with each request's final image "
-                         "MSE in both forms")
+                    help="measure serving instead: a Poisson stream of R requests of the "
+                         "mixed 2D/3D serving mix (prints its own JSON line)")
+    ap.add_argument("--serve-steps", type=int, default=500)
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=8,
+                    help="requests resident and stepping at once")
+    ap.add_argument("--serve-compare", type=int, default=0, metavar="Q",
+                    help="with --serve: also the first Q requests in FP32 one at a time "
+                         "against BF16 served together, with every request's final image MSE")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy before the steps (a "
                          "reference for hardware byte counters)")
@@ -165,57 +167,17 @@ def e_kernel_traffic():
     return int(m_b.group(1))
 
 
-def serve_bench(a):
-    """C5: R requests of the serving mix, each run alone and then all
-    together; throughput over all requests' steps, tick latencies, and a
-    check that every request ends with the parameters it had alone."""
-    import torch
-
-    from paper_2604_09884_amd import configs, synth
-    from paper_2604_09884_amd.serve import DONE, Request, Server
-
-    torch.cuda.set_device(0)
-    probs = configs.serving_mix(a.serve, steps=a.serve_steps)
+def _sinograms(probs):
+    """Seeded synthetic data of every request (closed-form chords, host work
+    done before any timing; large sinograms spread their views over threads)."""
+    from paper_2604_09884_amd import synth
+    out = []
     t0 = time.time()
-    reqs = [Request(problem=p, y=synth.sinogram(p).astype(np.float32), steps=p.steps)
-            for p in probs]
-    log("C5 mix: %s; sinograms in %.1f s" % ([p.name for p in probs], time.time() - t0))
-    # warm-up: one request of each architecture kind, one step
-    for r in reqs[:2]:
-        srv = Server(n_streams=1)
-        srv.submit(Request(problem=r.problem, y=r.y, steps=1))
-        srv.run()
-    torch.cuda.synchronize()
-    alone, t_seq = [], 0.0
-    for r in reqs:
-        srv = Server(n_streams=1)
-        rid = srv.submit(r)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        srv.run()
-        t_seq += time.perf_counter() - t
-        assert srv.status(rid).state == DONE, srv.status(rid).error
-        alone.append(srv.status(rid).theta)
-    srv = Server(n_streams=4)
-    ids = [srv.submit(r) for r in reqs]
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    srv.run()
-    t_mix = time.perf_counter() - t
-    same = all(srv.status(i).state == DONE and np.array_equal(srv.status(i).theta, th)
-               for i, th in zip(ids, alone))
-    m = srv.metrics()
-    steps = sum(r.steps for r in reqs)
-    out = {
-        "metric": "served grad steps/s (C5 serving mix)", "value": steps / t_mix,
-        "unit": "steps/s", "n_gpus": 1, "requests": len(reqs), "steps_per_request": a.serve_steps,
-        "sequential_steps_per_s": steps / t_seq, "speedup_vs_sequential": t_seq / t_mix,
-        "tick_ms_p50": m["tick_ms_p50"], "tick_ms_p99": m["tick_ms_p99"],
-        "mix_equals_alone": bool(same), "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": "C5 serving mix (seed 5005)",
-                   "requests": [p.name + ":" + p.arch.kind + ":" + p.mlp_dtype for p in probs]},
-    }
-    print(json.dumps(out), flush=True)
+    for i, p in enumerate(probs):
+        out.append(synth.sinogram(p).astype(np.float32))
+        if i % 8 == 7 or i == len(probs) - 1:
+            log("  sinograms %d/%d (%.1f s)" % (i + 1, len(probs), time.time() - t0))
+    return out
 
 
 def _fov_mask(dim, N):
@@ -224,75 +186,118 @@ def _fov_mask(dim, N):
     return disc if dim == 2 else np.broadcast_to(disc, (N, N, N))
 
 
-def serve_compare(a):
-    """The C5 mix in two forms: every request in FP32, one at a time, and
-    every request in BF16, served together; throughput of each and every
-    request's final image MSE (over the FOV, against the rasterised
-    phantom) in both."""
+def _final_mse(p, theta):
+    """Final-image MSE over the FOV against the rasterised phantom, with
+    the INR evaluated on the GPU in FP32."""
     import torch
 
-    from paper_2604_09884_amd import configs, ops, synth
-    from paper_2604_09884_amd.serve import DONE, Request, Server
+    from paper_2604_09884_amd import ops, synth
+    m = ops.Model(p.arch, p.dim, p.N, "fp32", max_k=1)
+    th = torch.tensor(theta, dtype=torch.float32, device="cuda")
+    _, B = synth.init_inr(p.arch, p.seed_init)
+    Bd = torch.tensor(B.ravel() if B.size else np.zeros(1), dtype=torch.float32, device="cuda")
+    u = ops.inr_eval_grid(m, th, Bd).cpu().numpy().reshape([p.N] * p.dim)
+    ref = synth.raster(synth.phantom(p), p.dim, p.N)
+    msk = _fov_mask(p.dim, p.N)
+    m.close()
+    return float(np.mean((u[msk] - ref[msk]) ** 2))
 
-    torch.cuda.set_device(0)
-    probs = configs.serving_mix(a.serve, steps=a.serve_steps)
-    ys = [synth.sinogram(p).astype(np.float32) for p in probs]
-    log("C5 mix for the comparison: %s" % [p.name for p in probs])
 
-    def final_mse(p, theta):
-        m = ops.Model(p.arch, p.dim, p.N, "fp32", max_k=1)
-        th = torch.tensor(theta, dtype=torch.float32, device="cuda")
-        _, B = synth.init_inr(p.arch, p.seed_init)
-        Bd = torch.tensor(B.ravel() if B.size else np.zeros(1), dtype=torch.float32,
-                          device="cuda")
-        u = ops.inr_eval_grid(m, th, Bd).cpu().numpy().reshape([p.N] * p.dim)
-        ref = synth.raster(synth.phantom(p), p.dim, p.N)
-        msk = _fov_mask(p.dim, p.N)
-        m.close()
-        return float(np.mean((u[msk] - ref[msk]) ** 2))
+def _serve(probs, ys, arrivals, dtype, n_slots, depth=2):
+    """Runs the requests through one server (arrival times on its clock;
+    None: all at once) and returns (server, request ids)."""
+    import torch
 
-    # warm-up, both precisions
-    for dt in ("fp32", "bf16"):
-        srv = Server(n_streams=1)
-        srv.submit(Request(problem=probs[0], y=ys[0], steps=1, mlp_dtype=dt))
-        srv.run()
+    from paper_2604_09884_amd.serve import Request, Server
+    srv = Server(n_slots=n_slots, depth=depth)
+    ids = [srv.submit(Request(problem=p, y=y, steps=p.steps, mlp_dtype=dtype),
+                      arrival=None if arrivals is None else float(t))
+           for p, y, t in zip(probs, ys, arrivals if arrivals is not None else [0] * len(probs))]
     torch.cuda.synchronize()
-    t_a, mse_a = 0.0, []
-    for p, y in zip(probs, ys):
-        srv = Server(n_streams=1)
-        rid = srv.submit(Request(problem=p, y=y, steps=p.steps, mlp_dtype="fp32"))
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        srv.run()
-        t_a += time.perf_counter() - t
-        assert srv.status(rid).state == DONE, srv.status(rid).error
-        mse_a.append(final_mse(p, srv.status(rid).theta))
-        log("FP32 alone: %s final MSE %.4g" % (p.name, mse_a[-1]))
-    srv = Server(n_streams=4)
-    ids = [srv.submit(Request(problem=p, y=y, steps=p.steps, mlp_dtype="bf16"))
-           for p, y in zip(probs, ys)]
-    torch.cuda.synchronize()
-    t = time.perf_counter()
+    srv.t0 = time.perf_counter()
+    for i in ids:  # arrival times count from the start of the run
+        if arrivals is None:
+            srv.slots[i].t_arrive = 0.0
     srv.run()
-    t_b = time.perf_counter() - t
+    torch.cuda.synchronize()
+    return srv, ids
+
+
+def serve_bench(a):
+    """The serving workload: a seeded Poisson stream of requests (mean rate
+    --serve-rate per second) from the mixed 2D/3D request mix, each a
+    --serve-steps-step fit, served with continuous batching in BF16.
+    Reports time-to-reconstruction percentiles (completion minus arrival),
+    aggregate steps/s and makespan.  With --serve-compare Q, the first Q
+    requests are also run in FP32 one at a time (back to back) and in BF16
+    served together, with each request's final image MSE in both forms."""
+    import torch
+
+    from paper_2604_09884_amd import configs
+    from paper_2604_09884_amd.serve import DONE, poisson_arrivals
+
+    probs = configs.serving_mix(a.serve, steps=a.serve_steps)
+    arrivals = poisson_arrivals(len(probs), a.serve_rate, 5005)
+    t0 = time.time()
+    ys = _sinograms(probs)
+    log("serving stream: %d requests over %.1f s of arrivals; sinograms in %.1f s"
+        % (len(probs), arrivals[-1], time.time() - t0))
+    torch.cuda.set_device(0)
+    # warm-up: one request of each kind for one step (kernel loading)
+    seen = set()
+    warm = []
+    for p, y in zip(probs, ys):
+        key = (p.dim, p.arch.kind)
+        if key not in seen:
+            seen.add(key)
+            warm.append((p.with_(steps=1), y))
+    _serve([w[0] for w in warm], [w[1] for w in warm], None, "bf16", a.serve_slots)
+    srv, ids = _serve(probs, ys, arrivals, "bf16", a.serve_slots)
     m = srv.metrics()
-    mse_b = []
-    for p, i in zip(probs, ids):
-        assert srv.status(i).state == DONE, srv.status(i).error
-        mse_b.append(final_mse(p, srv.status(i).theta))
-        log("BF16 served: %s final MSE %.4g" % (p.name, mse_b[-1]))
-    steps = sum(p.steps for p in probs)
-    rel = [abs(b - f) / f for f, b in zip(mse_a, mse_b)]
+    bad = [srv.status(i).error for i in ids if srv.status(i).state != DONE]
+    log("served: %s%s" % ({k: round(v, 3) if isinstance(v, float) else v
+                           for k, v in m.items()}, " failures %s" % bad if bad else ""))
     out = {
-        "metric": "served BF16 vs one-at-a-time FP32 grad steps/s (C5 serving mix)",
-        "value": steps / t_b, "unit": "steps/s", "n_gpus": 1, "requests": len(probs),
-        "steps_per_request": a.serve_steps, "fp32_one_at_a_time_steps_per_s": steps / t_a,
-        "speedup": t_a / t_b, "tick_ms_p50": m["tick_ms_p50"], "tick_ms_p99": m["tick_ms_p99"],
-        "final_mse_fp32_alone": mse_a, "final_mse_bf16_served": mse_b,
-        "max_rel_mse_difference": max(rel), "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": "C5 serving mix (seed 5005)",
-                   "requests": [p.name + ":" + p.arch.kind for p in probs]},
+        "metric": "p99 recon latency (served mixed 2D/3D stream)",
+        "value": m["latency_s_p99"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "latency_s": {"p50": m["latency_s_p50"], "p95": m["latency_s_p95"],
+                      "p99": m["latency_s_p99"], "max": m["latency_s_max"]},
+        "queue_wait_s": {"p50": m["queue_wait_s_p50"], "p99": m["queue_wait_s_p99"]},
+        "steps_per_s": m["steps_per_s"], "makespan_s": m["makespan_s"],
+        "requests": len(probs), "done": m["done"], "failed": m["failed"],
+        "steps_per_request": a.serve_steps, "arrival_rate_per_s": a.serve_rate,
+        "slots": a.serve_slots, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "C5 serving stream (Poisson arrivals seed 5005, mix seed 5005)",
+                   "mix": [p.name + ":" + p.arch.kind for p in probs]},
     }
+    if a.serve_compare:
+        q = min(a.serve_compare, len(probs))
+        sub, suby = probs[:q], ys[:q]
+        t = time.perf_counter()
+        alone = []
+        for p, y in zip(sub, suby):
+            s1, i1 = _serve([p], [y], None, "fp32", 1)
+            assert s1.status(i1[0]).state == DONE, s1.status(i1[0]).error
+            alone.append(s1.status(i1[0]).theta)
+            log("FP32 alone: %s done" % p.name)
+        t_fp32 = time.perf_counter() - t
+        t = time.perf_counter()
+        s2, i2 = _serve(sub, suby, None, "bf16", a.serve_slots)
+        t_bf16 = time.perf_counter() - t
+        mse32 = [_final_mse(p, th) for p, th in zip(sub, alone)]
+        mse16 = [_final_mse(p, s2.status(i).theta) for p, i in zip(sub, i2)]
+        rel = [abs(b - f) / f for f, b in zip(mse32, mse16)]
+        steps = sum(p.steps for p in sub)
+        out["compare"] = {
+            "requests": q, "steps_per_request": a.serve_steps,
+            "fp32_one_at_a_time_steps_per_s": steps / t_fp32,
+            "bf16_served_steps_per_s": steps / t_bf16, "speedup": t_fp32 / t_bf16,
+            "final_mse_fp32_alone": mse32, "final_mse_bf16_served": mse16,
+            "max_rel_mse_difference": max(rel), "median_rel_mse_difference": float(np.median(rel)),
+            "mix": [p.name + ":" + p.arch.kind for p in sub],
+        }
+        log("compare: FP32 alone %.1f steps/s, BF16 served %.1f steps/s, max rel MSE diff %.3g"
+            % (steps / t_fp32, steps / t_bf16, max(rel)))
     print(json.dumps(out), flush=True)
 
 
@@ -303,10 +308,7 @@ def main():
               "(requested --gpus %d)" % a.gpus, flush=True)
         sys.exit(2)
     if a.serve:
-        if a.serve_compare:
-            serve_compare(a)
-        else:
-            serve_bench(a)
+        serve_bench(a)
         return
     import torch
 

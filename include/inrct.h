@@ -19,12 +19,20 @@
  *    current HIP device; the caller owns them.  Host pointers are read
  *    before the call returns and may be freed afterwards.
  *  - Calls that take a hipStream_t only enqueue work on that stream; none
- *    synchronises with the host and none allocates device memory.  Device
- *    memory is allocated only by the *_create functions.
+ *    synchronises with the host or the device and none allocates device
+ *    memory.
+ *  - Device memory: every handle (geometry, model, context) keeps its
+ *    tables and scratch in one workspace of exactly
+ *    inrct_workspace_bytes(...) bytes, which the caller passes to the
+ *    *_create call (`ws`, `ws_bytes`: device memory, 256-byte aligned, owned
+ *    by the caller and kept alive until the handle is destroyed).  With
+ *    ws == NULL the create call allocates that workspace itself and the
+ *    destroy call frees it; nothing else in the library allocates.  A create
+ *    call enqueues its table uploads and fills on its `stream`; work that
+ *    uses the handle must be ordered after that stream.
  *  - Outputs are overwritten, never accumulated into.
- *  - A handle (geometry, model, context) owns scratch memory; it may be used
- *    by one stream at a time.  Calls that overlap on different streams must
- *    use different handles.
+ *  - A handle's scratch may be used by one stream at a time.  Calls that
+ *    overlap on different streams must use different handles.
  *  - Every entry point returns INRCT_OK (0) or a negative status; after an
  *    error, inrct_last_error() returns a message (thread-local).  Argument
  *    errors are detected on the host before anything is enqueued.
@@ -137,6 +145,24 @@ typedef struct inr_ctx inr_ctx;
 /* Message for the most recent error on this thread ("" if none). */
 const char *inrct_last_error(void);
 
+/* workspace kinds */
+#define INRCT_WS_GEOM 1     /* inrct_geom_create: needs g, grid             */
+#define INRCT_WS_MODEL 2    /* inrct_model_create: needs arch, grid, max_k  */
+#define INRCT_WS_CTX 3      /* inr_ctx_create: arch, g, grid, max_k, cfg    */
+
+typedef struct inrct_step_cfg inrct_step_cfg;
+
+/* Exact device bytes the workspace of a handle needs: the geometry handle
+ * of (g, grid), the model handle of (arch, grid, max_k), or the context of
+ * such a model and geometry with step configuration cfg.  Arguments a kind
+ * does not use may be NULL.  Runs only host arithmetic (the handle's build
+ * code in a counting mode), so a caller can budget device memory before
+ * creating anything.  Returns the byte count, or a negative status with
+ * the same argument checks as the create call. */
+int64_t inrct_workspace_bytes(int which, const inr_arch *arch,
+                              const ct_geometry *g, const inr_grid *grid,
+                              int64_t max_k, const inrct_step_cfg *cfg);
+
 /* ------------------------------------------------------------------ P, P^T
  * Joseph's ray-driven projector (Sec. III: P in R^{m x n}, a discrete
  * approximation of ray integrals).  Per ray: one sample per grid slice
@@ -147,10 +173,13 @@ const char *inrct_last_error(void);
  * point from float64 ray parameters, so P and P^T see identical weights.
  */
 
-/* Builds the geometry tables (host float64) and uploads them; allocates the
- * handle's device scratch.  `g` and `grid` are copied. */
-int inrct_geom_create(const ct_geometry *g, const inr_grid *grid,
-                      inrct_geom **out);
+/* Builds the geometry tables (host float64) and uploads them into the
+ * handle's workspace (see the conventions above; size from
+ * inrct_workspace_bytes(INRCT_WS_GEOM, ...)).  `g` and `grid` are copied.
+ * CONE3D fails with INRCT_EINVAL if any detector row is steeper in z than
+ * along its ray's in-plane principal axis. */
+int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, void *ws,
+                      size_t ws_bytes, hipStream_t stream, inrct_geom **out);
 int inrct_geom_destroy(inrct_geom *geom);
 /* number of rays m = n_views * n_v * n_u */
 int64_t inrct_geom_n_rays(const inrct_geom *geom);
@@ -185,9 +214,12 @@ int inrct_residual_loss(inrct_geom *geom, int loss, const float *z,
 /* ------------------------------------------------------------------ E, VJP
  * INR f_theta (Sec. IV: FFN and SIREN) evaluated with matrix-core GEMMs.
  * `max_k` bounds the k of later inr_vjp_subsampled / inrct_sample calls
- * (it sizes the handle's scratch).  `arch` and `grid` are copied. */
+ * (it sizes the handle's scratch; workspace from
+ * inrct_workspace_bytes(INRCT_WS_MODEL, ...)).  `arch` and `grid` are
+ * copied. */
 int inrct_model_create(const inr_arch *arch, const inr_grid *grid,
-                       int64_t max_k, inrct_model **out);
+                       int64_t max_k, void *ws, size_t ws_bytes,
+                       hipStream_t stream, inrct_model **out);
 int inrct_model_destroy(inrct_model *model);
 int64_t inrct_model_n_params(const inrct_model *model);
 int64_t inrct_model_n_fov(const inrct_model *model);
@@ -234,21 +266,23 @@ int inrct_adam(inrct_model *model, float *theta, float *m, float *v,
                hipStream_t stream);
 
 /* ------------------------------------------------------------ full step */
-typedef struct {
+struct inrct_step_cfg {
     int loss;               /* INRCT_LS or INRCT_FLS                        */
     int64_t k;              /* |I|; k == n is full sampling                 */
     uint64_t seed;          /* sampler key                                  */
     double lr, beta1, beta2, eps;
     int v_mode;             /* INRCT_V_FULL or INRCT_V_AT_I                 */
-} inrct_step_cfg;
+};
 
 /* A context binds a model, a geometry and caller-owned device buffers
- * theta [p], adam_m [p], adam_v [p], B [F][d] (or NULL) and y [rays].  It
- * allocates its own u, z/r, v, g and I buffers. */
+ * theta [p], adam_m [p], adam_v [p], B [F][d] (or NULL) and y [rays].  Its
+ * own u, z/r, v, g and I buffers live in its workspace
+ * (inrct_workspace_bytes(INRCT_WS_CTX, ...)); u outside the FOV is cleared
+ * on `stream`. */
 int inr_ctx_create(inrct_model *model, inrct_geom *geom,
                    const inrct_step_cfg *cfg, float *theta, float *adam_m,
-                   float *adam_v, const float *B, const float *y,
-                   inr_ctx **out);
+                   float *adam_v, const float *B, const float *y, void *ws,
+                   size_t ws_bytes, hipStream_t stream, inr_ctx **out);
 int inr_ctx_destroy(inr_ctx *ctx);
 
 /* One Algorithm-1 gradient estimate followed by one Adam update, all on

@@ -20,7 +20,7 @@ void clear_error() { g_last_error.clear(); }
 
 const char *last_error() { return g_last_error.c_str(); }
 
-void FovHost::build(int dim, int N) {
+void FovHost::build(Arena &ar, int dim, int N) {
     xlo.assign(N, 0);
     cnt.assign(N, 0);
     row_start.assign(N + 1, 0);
@@ -47,8 +47,8 @@ void FovHost::build(int dim, int N) {
     row_start[N] = (int32_t)acc;
     n_slice = acc;
     n = acc * (dim == 3 ? N : 1);
-    upload(d_xlo, xlo);
-    upload(d_row_start, row_start);
+    upload(ar, d_xlo, xlo);
+    upload(ar, d_row_start, row_start);
 }
 
 __global__ void k_sum_partials(const double *p, int n, double *out) {

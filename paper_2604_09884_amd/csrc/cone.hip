@@ -29,7 +29,7 @@ static const int kPad = 2;  // zero border of the padded volume copies
 static const unsigned kConeFwdLdsCap = 54 * 1024;  // occupancy cap of k_cone_fwd
 
 // ------------------------------------------------------------------ host
-void cone_build(inrct_geom *hd) {
+void cone_build(inrct_geom *hd, Arena &ar) {
     const ct_geometry &g = hd->g;
     const int N = hd->N;
     const double h = 2.0 / N;
@@ -62,6 +62,11 @@ void cone_build(inrct_geom *hd) {
             const double t0 = (c0 - pax) * inv;
             const double tN = t0 + (N - 1) * h * inv;
             INRCT_REQUIRE(t0 > 0 && tN > 0, "a grid slice lies behind the source");
+            // Joseph needs every ray shallower in z than along its principal
+            // axis; the steepest rays of the column are its end rows
+            INRCT_REQUIRE(fabs(dz0) + cv * g.dv < fabs(dax),
+                          "view %d column %d: the end rows are steeper in z than along the "
+                          "principal axis (detector too tall)", j, a);
             const double phio = (pot + t0 * dot + 1.0) / h - 0.5;
             c.F0o = llrint(phio * kFix40);
             c.dFo = llrint(dot * inv * kFix40);
@@ -76,17 +81,16 @@ void cone_build(inrct_geom *hd) {
             if (c.ypr) vg.any_y = 1; else { vg.any_x = 1; any_x = true; }
         }
     }
-    upload(hd->ccols, cols);
-    upload(hd->cviews, views);
+    upload(ar, hd->ccols, cols);
+    upload(ar, hd->cviews, views);
     hd->any_x = any_x;
     // zero-bordered copies of u in both layouts ([z][y][x] and [z][x][y]);
     // the border is cleared once here and never written afterwards
     const size_t Np = (size_t)N + 2 * kPad;
     // the projector addresses the padded copy with 32-bit element offsets
     INRCT_REQUIRE(Np * Np * Np < ((size_t)1 << 31), "cone-beam grid n = %d exceeds 1286", N);
-    hd->ut.alloc(sizeof(float) * Np * Np * Np * (any_x ? 2 : 1));
-    INRCT_CHECK_HIP(hipMemset(hd->ut.ptr, 0, hd->ut.bytes));
-    INRCT_CHECK_HIP(hipDeviceSynchronize());
+    hd->ut.alloc(ar, sizeof(float) * Np * Np * Np * (any_x ? 2 : 1));
+    zero_fill(ar, hd->ut);
 }
 
 // ---------------------------------------------------------------- device

@@ -60,6 +60,7 @@ struct ConeDev {
 }  // namespace inrct
 
 struct inrct_geom {
+    inrct::Workspace ws;
     ct_geometry g;
     int N = 0, dim = 0;
     std::vector<double> angles;
@@ -101,7 +102,10 @@ struct inrct_geom {
 };
 
 namespace inrct {
-void cone_build(inrct_geom *h);
+void cone_build(inrct_geom *h, Arena &a);
+void check_geom_args(const ct_geometry *g, const inr_grid *grid);
+inrct_geom *fresh_geom(const ct_geometry *g, const inr_grid *grid);
+void build_geom(inrct_geom *h, Arena &ar);
 void cone_project(inrct_geom *h, const float *u, float *z, hipStream_t s);
 void cone_backproject(inrct_geom *h, const float *r, float *v, hipStream_t s);
 void cone_backproject_at(inrct_geom *h, const float *r, const int32_t *idx, int64_t k,

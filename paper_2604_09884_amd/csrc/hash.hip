@@ -417,7 +417,7 @@ void hash_vjp(inrct_model *m, const float *theta, const int32_t *idx, long long 
     INRCT_CHECK_LAUNCH();
 }
 
-void hash_setup(inrct_model *m) {
+void hash_setup(inrct_model *m, Arena &ar) {
     const inr_arch &a = m->arch;
     const int Lh = a.hash_levels;
     const double b = Lh == 1 ? 1.0
@@ -435,18 +435,18 @@ void hash_setup(inrct_model *m) {
         off += (long long)fi * fo + fo;
     }
     m->n_params = off;
-    upload(m->d_loff, m->loff);
+    upload(ar, m->d_loff, m->loff);
     const long long kmax = m->max_k;
     m->hash_row = K + 2 * L * W + 1;
-    m->hash_rows.alloc(sizeof(float) * (size_t)kmax * m->hash_row);
+    m->hash_rows.alloc(ar, sizeof(float) * (size_t)kmax * m->hash_row);
     const int nv = m->dim == 3 ? 8 : 4;
     const long long nc = kmax * Lh * nv;
     INRCT_REQUIRE(nc < (1LL << 31), "too many hash-table contributions (max_k x levels x 2^d)");
-    m->hash_key.alloc(sizeof(uint32_t) * nc);
-    m->hash_pos.alloc(sizeof(uint32_t) * nc);
-    m->hash_skey.alloc(sizeof(uint32_t) * nc);
-    m->hash_spos.alloc(sizeof(uint32_t) * nc);
-    m->hash_val.alloc(sizeof(float2) * nc);
+    m->hash_key.alloc(ar, sizeof(uint32_t) * nc);
+    m->hash_pos.alloc(ar, sizeof(uint32_t) * nc);
+    m->hash_skey.alloc(ar, sizeof(uint32_t) * nc);
+    m->hash_spos.alloc(ar, sizeof(uint32_t) * nc);
+    m->hash_val.alloc(ar, sizeof(float2) * nc);
     int bits = 1;
     while ((1LL << bits) < (long long)Lh * T) ++bits;
     m->hash_key_bits = bits;
@@ -454,9 +454,9 @@ void hash_setup(inrct_model *m) {
     INRCT_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint32_t *)nullptr,
                                                        (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                        (uint32_t *)nullptr, (int)nc, 0, bits));
-    m->hash_tmp.alloc(std::max<size_t>(tb, 256));
+    m->hash_tmp.alloc(ar, std::max<size_t>(tb, 256));
     const long long n_mlp = m->n_params - (long long)Lh * T * 2;
-    m->hash_part.alloc(sizeof(float) * (size_t)cdiv(kmax, kHashSlice) * n_mlp);
+    m->hash_part.alloc(ar, sizeof(float) * (size_t)cdiv(kmax, kHashSlice) * n_mlp);
 }
 
 }  // namespace inrct

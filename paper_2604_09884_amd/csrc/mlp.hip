@@ -1923,241 +1923,267 @@ void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t
 
 }  // namespace inrct
 
+namespace inrct {
+// Argument checks of inrct_model_create.
+void check_model_args(const inr_arch *arch, const inr_grid *grid, int64_t max_k) {
+    INRCT_REQUIRE(arch && grid, "null argument");
+    const inr_arch &a = *arch;
+    INRCT_REQUIRE(grid->dim == 2 || grid->dim == 3, "grid dim must be 2 or 3");
+    INRCT_REQUIRE(grid->n >= 1 && grid->n <= 4096, "grid n must be in [1, 4096]");
+    INRCT_REQUIRE(a.in_dim == grid->dim, "arch in_dim must equal the grid dim");
+    INRCT_REQUIRE(a.kind == INRCT_FFN || a.kind == INRCT_SIREN || a.kind == INRCT_HASH,
+                  "unknown INR kind %d", a.kind);
+    if (a.kind == INRCT_HASH) {
+        INRCT_REQUIRE(a.width == 16 || a.width == 32 || a.width == 64,
+                      "hash INR width must be 16, 32 or 64");
+        INRCT_REQUIRE(a.depth >= 1 && a.depth <= kHashMaxDepth && a.width * a.depth <= 128,
+                      "hash INR needs 1 <= depth <= 4 and width * depth <= 128");
+        INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32, "hash INR runs in FP32");
+        INRCT_REQUIRE(a.hash_levels >= 1 && a.hash_levels <= kHashMaxLevels,
+                      "hash levels must be in [1, %d]", kHashMaxLevels);
+        INRCT_REQUIRE(a.hash_log2_size >= 4 && a.hash_log2_size <= 24,
+                      "hash table size must be 2^4 .. 2^24");
+        INRCT_REQUIRE(a.hash_base_res >= 1 && a.hash_max_res >= a.hash_base_res &&
+                          a.hash_max_res <= (1 << 20),
+                      "hash resolutions must satisfy 1 <= base <= max <= 2^20");
+    } else {
+        INRCT_REQUIRE(a.width == 128 || a.width == 256, "width must be 128 or 256");
+        INRCT_REQUIRE(a.depth >= 1 && a.depth <= kMaxDepth, "depth must be in [1, %d]",
+                      kMaxDepth);
+    }
+    INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32 || a.mlp_dtype == INRCT_BF16, "unknown mlp dtype");
+    if (a.kind == INRCT_FFN)
+        INRCT_REQUIRE(a.n_freq >= 8 && a.n_freq % 8 == 0 && a.n_freq <= 4096,
+                      "FFN needs n_freq a positive multiple of 8");
+    INRCT_REQUIRE(max_k >= 1, "max_k must be >= 1");
+}
+
+// Everything a model handle holds on the device, carved from `ar` (arch, N,
+// dim and max_k already set).  Run once to size the workspace and once to
+// carve it.
+void build_model(inrct_model *m, Arena &ar) {
+    const inr_arch &a = m->arch;
+    m->n_grid = 1;
+    for (int i = 0; i < m->dim; ++i) m->n_grid *= m->N;
+    INRCT_REQUIRE(m->n_grid < (1LL << 31), "grid too large for int32 indices");
+    m->fov.build(ar, m->dim, m->N);
+    {
+        // compute units of the current device (they size the dW split); with
+        // no device (sizing on a host without a GPU) an MI355X's 256
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 0;
+        (void)hipGetLastError();
+        m->n_cu = ncu > 0 ? ncu : 256;
+    }
+    m->n_fov = m->fov.n;
+    INRCT_REQUIRE(m->n_fov >= 1, "empty FOV");
+    m->max_k = std::min<long long>(m->max_k, m->n_fov);
+    if (a.kind == INRCT_HASH) {
+        hash_setup(m, ar);
+        // sampler scratch and Adam partials, as below
+        m->flags.alloc(ar, (size_t)m->n_fov);
+        m->n_blk = cdiv(m->n_fov, 4096);
+        m->blk.alloc(ar, (size_t)(m->n_blk + 1) * sizeof(int64_t));
+        m->n_apart = adam_partials(m->n_params);
+        m->apart.alloc(ar, sizeof(double) * m->n_apart);
+        return;
+    }
+    const int W = a.width, L = a.depth, d = a.in_dim;
+    const bool bf = a.mlp_dtype == INRCT_BF16;
+    const int kps = bf ? 16 : 2;
+    // parameter offsets
+    m->loff.assign(L + 2, 0);
+    long long off = 0;
+    for (int l = 1; l <= L + 1; ++l) {
+        m->loff[l] = off;
+        const int K = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
+        const int O = l == L + 1 ? 1 : W;
+        off += (long long)K * O + O;
+    }
+    m->n_params = off;
+    upload(ar, m->d_loff, m->loff);
+    // fragment tables
+    std::vector<int> fl, fm, fs;
+    const int MT = W / 32;
+    const int l_first = a.kind == INRCT_FFN ? 1 : 2;
+    for (int l = l_first; l <= L; ++l) {
+        const int KS = ksteps(layer_K(a.kind, a.n_freq, d, W, l), kps);
+        m->frag_off[l] = (long long)fl.size();
+        for (int s = 0; s < KS; ++s)
+            for (int mt = 0; mt < MT; ++mt) {
+                fl.push_back(l);
+                fm.push_back(mt);
+                fs.push_back(s);
+            }
+    }
+    m->nfrag = (long long)fl.size();
+    for (int l = 2; l <= L; ++l) {
+        const int NS = W / kps;
+        m->fragT_off[l] = (long long)fl.size() - m->nfrag;
+        for (int s = 0; s < NS; ++s)
+            for (int mt = 0; mt < MT; ++mt) {
+                fl.push_back(l);
+                fm.push_back(mt);
+                fs.push_back(s);
+            }
+    }
+    m->nfragT = (long long)fl.size() - m->nfrag;
+    if (bf && W == 256) {
+        // chunk stream of the width-256 LDS kernel (biases excluded):
+        // layer 1 by k-step x 8 M-tiles, hidden layers by half, then
+        // k-step x 4 M-tiles
+        std::vector<int> hl, hm, hs;
+        if (a.kind == INRCT_FFN) {
+            const int KS1 = ksteps(layer_K(a.kind, a.n_freq, d, W, 1), 16) - 1;
+            for (int s = 0; s < KS1; ++s)
+                for (int mt = 0; mt < 8; ++mt) {
+                    hl.push_back(1);
+                    hm.push_back(mt);
+                    hs.push_back(s);
+                }
+        }
+        for (int l = 2; l <= L; ++l)
+            for (int half = 0; half < 2; ++half)
+                for (int s = 0; s < 16; ++s)
+                    for (int mt = 0; mt < 4; ++mt) {
+                        hl.push_back(l);
+                        hm.push_back(half * 4 + mt);
+                        hs.push_back(s);
+                    }
+        m->nfrag_h = (long long)hl.size();
+        upload(ar, m->pkh_layer, hl);
+        upload(ar, m->pkh_mt, hm);
+        upload(ar, m->pkh_s, hs);
+        m->frag_h.alloc(ar, m->nfrag_h * 64 * 16);
+        m->vjp_lds = a.kind == INRCT_FFN && a.n_freq % 32 == 0 &&
+                     a.n_freq <= 512 && L >= 2 && L <= kMaxDepthV;
+        if (m->vjp_lds) {
+            // backward stream: layers L .. 2, by half, k-step x 4 M-tiles
+            // of W_l^T (M-tiles over the inputs of layer l)
+            std::vector<int> vl = hl, vm = hm, vs = hs;
+            for (int l = L; l >= 2; --l)
+                for (int half = 0; half < 2; ++half)
+                    for (int s = 0; s < 16; ++s)
+                        for (int mt = 0; mt < 4; ++mt) {
+                            vl.push_back(l);
+                            vm.push_back(half * 4 + mt);
+                            vs.push_back(s);
+                        }
+            m->nfrag_vb = (long long)vl.size() - m->nfrag_h;
+            upload(ar, m->pkv_layer, vl);
+            upload(ar, m->pkv_mt, vm);
+            upload(ar, m->pkv_s, vs);
+            m->frag_v.alloc(ar, (m->nfrag_h + m->nfrag_vb) * 64 * 16);
+        }
+    }
+    upload(ar, m->pk_layer, fl);
+    upload(ar, m->pk_mt, fm);
+    upload(ar, m->pk_s, fs);
+    const size_t fbytes = bf ? 16 : 4;
+    m->frag.alloc(ar, std::max<long long>(1, m->nfrag) * 64 * fbytes);
+    m->fragT.alloc(ar, std::max<long long>(1, m->nfragT) * 64 * fbytes);
+    // VJP scratch: chunk of P_alloc points
+    const long long kpad = cdiv(m->max_k, 256) * 256;
+    m->P_alloc = std::min<long long>(kpad, 262144);
+    m->nks = (int)cdiv(m->P_alloc, m->kslice);
+    const long long P = m->P_alloc;
+    const int K1 = layer_K(a.kind, a.n_freq, d, W, 1);
+    m->act_off[0] = 0;
+    for (int l = 1; l <= L; ++l) m->act_off[l] = (long long)K1 * P + (long long)(l - 1) * W * P;
+    m->act_elems = (long long)K1 * P + (long long)L * W * P;
+    m->dlt_elems = (long long)L * W * P + P;
+    const size_t es = bf ? 2 : 4;
+    m->act.alloc(ar, m->act_elems * es);
+    m->mask.alloc(ar, sizeof(uint4) * (size_t)std::max(1, L - 1) * (P / 32) * 64);
+    m->dlt.alloc(ar, m->dlt_elems * es);
+    if (a.kind == INRCT_SIREN) {
+        for (int l = 1; l <= L; ++l) m->sig_off[l] = (long long)(l - 1) * W * P;
+        m->sig_elems = (long long)L * W * P;
+        m->sig.alloc(ar, m->sig_elems * sizeof(float));
+    }
+    if (bf) {
+        // full-width dW tiles: layer l = 1..L+1, 256 input columns each
+        std::vector<GemmTile2> tiles2;
+        for (int l = 1; l <= L + 1; ++l) {
+            GemmTile2 t{};
+            t.M = l == L + 1 ? 1 : W;
+            t.R = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
+            t.dlt_off = (long long)(l - 1) * W * P;
+            t.act_off = m->act_off[l - 1];
+            t.theta_off = m->loff[l];
+            for (int tn = 0; tn < t.R; tn += 256) {
+                GemmTile2 u = t;
+                u.tn = tn;
+                u.bias = tn == 0;
+                tiles2.push_back(u);
+            }
+        }
+        m->ntiles = (int)tiles2.size();
+        upload(ar, m->tiles, tiles2);
+        // split-K slices of 2048 points, shortened (to no less than
+        // 512) when the chunk is too small to give every CU a block
+        const long long want = cdiv((long long)m->n_cu, (long long)m->ntiles);
+        const long long ks = cdiv(cdiv(P, want), 256) * 256;
+        m->kslice = (int)std::min<long long>(2048, std::max<long long>(512, ks));
+        m->nks = (int)cdiv(P, m->kslice);
+        m->part.alloc(ar, (size_t)m->nks * m->ntiles * kDwPart * sizeof(float));
+    }
+    // dW GEMM tiles: layer l = 1..L+1, delta rows M, inputs R (+ bias col)
+    std::vector<GemmTile> tiles;
+    for (int l = 1; l <= L + 1; ++l) {
+        GemmTile t{};
+        t.M = l == L + 1 ? 1 : W;
+        t.R = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
+        t.dlt_off = (long long)(l - 1) * W * P;
+        t.act_off = m->act_off[l - 1];
+        t.theta_off = m->loff[l];
+        for (int tm = 0; tm < t.M; tm += 128)
+            for (int tn = 0; tn <= t.R; tn += 128) {
+                GemmTile u = t;
+                u.tm = tm;
+                u.tn = tn;
+                tiles.push_back(u);
+            }
+    }
+    if (!bf) {
+        m->ntiles = (int)tiles.size();
+        upload(ar, m->tiles, tiles);
+        m->part.alloc(ar, (size_t)m->nks * m->ntiles * 16384 * sizeof(float));
+    }
+    // sampler scratch
+    m->flags.alloc(ar, (size_t)m->n_fov);
+    m->n_blk = cdiv(m->n_fov, 4096);
+    m->blk.alloc(ar, (size_t)(m->n_blk + 1) * sizeof(int64_t));
+    // Adam partials
+    m->n_apart = adam_partials(m->n_params);
+    m->apart.alloc(ar, sizeof(double) * m->n_apart);
+}
+
+inrct_model *fresh_model(const inr_arch *arch, const inr_grid *grid, int64_t max_k) {
+    inrct_model *m = new inrct_model();
+    m->arch = *arch;
+    m->N = grid->n;
+    m->dim = grid->dim;
+    m->max_k = max_k;
+    return m;
+}
+}  // namespace inrct
+
 extern "C" {
 
-int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k,
-                       inrct_model **out) {
+int inrct_model_create(const inr_arch *arch, const inr_grid *grid, int64_t max_k, void *ws,
+                       size_t ws_bytes, hipStream_t stream, inrct_model **out) {
     return guarded([&] {
-        INRCT_REQUIRE(arch && grid && out, "null argument");
+        INRCT_REQUIRE(out, "null argument");
         *out = nullptr;
-        const inr_arch &a = *arch;
-        INRCT_REQUIRE(grid->dim == 2 || grid->dim == 3, "grid dim must be 2 or 3");
-        INRCT_REQUIRE(grid->n >= 1 && grid->n <= 4096, "grid n must be in [1, 4096]");
-        INRCT_REQUIRE(a.in_dim == grid->dim, "arch in_dim must equal the grid dim");
-        INRCT_REQUIRE(a.kind == INRCT_FFN || a.kind == INRCT_SIREN || a.kind == INRCT_HASH,
-                      "unknown INR kind %d", a.kind);
-        if (a.kind == INRCT_HASH) {
-            INRCT_REQUIRE(a.width == 16 || a.width == 32 || a.width == 64,
-                          "hash INR width must be 16, 32 or 64");
-            INRCT_REQUIRE(a.depth >= 1 && a.depth <= kHashMaxDepth && a.width * a.depth <= 128,
-                          "hash INR needs 1 <= depth <= 4 and width * depth <= 128");
-            INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32, "hash INR runs in FP32");
-            INRCT_REQUIRE(a.hash_levels >= 1 && a.hash_levels <= kHashMaxLevels,
-                          "hash levels must be in [1, %d]", kHashMaxLevels);
-            INRCT_REQUIRE(a.hash_log2_size >= 4 && a.hash_log2_size <= 24,
-                          "hash table size must be 2^4 .. 2^24");
-            INRCT_REQUIRE(a.hash_base_res >= 1 && a.hash_max_res >= a.hash_base_res &&
-                              a.hash_max_res <= (1 << 20),
-                          "hash resolutions must satisfy 1 <= base <= max <= 2^20");
-        } else {
-            INRCT_REQUIRE(a.width == 128 || a.width == 256, "width must be 128 or 256");
-            INRCT_REQUIRE(a.depth >= 1 && a.depth <= kMaxDepth, "depth must be in [1, %d]",
-                          kMaxDepth);
-        }
-        INRCT_REQUIRE(a.mlp_dtype == INRCT_FP32 || a.mlp_dtype == INRCT_BF16, "unknown mlp dtype");
-        if (a.kind == INRCT_FFN)
-            INRCT_REQUIRE(a.n_freq >= 8 && a.n_freq % 8 == 0 && a.n_freq <= 4096,
-                          "FFN needs n_freq a positive multiple of 8");
-        INRCT_REQUIRE(max_k >= 1, "max_k must be >= 1");
-        inrct_model *m = new inrct_model();
+        check_model_args(arch, grid, max_k);
+        inrct_model *m = fresh_model(arch, grid, max_k);
         try {
-            m->arch = a;
-            m->N = grid->n;
-            m->dim = grid->dim;
-            m->n_grid = 1;
-            for (int i = 0; i < m->dim; ++i) m->n_grid *= m->N;
-            INRCT_REQUIRE(m->n_grid < (1LL << 31), "grid too large for int32 indices");
-            m->fov.build(m->dim, m->N);
-            {
-                int dev = 0, ncu = 0;
-                INRCT_CHECK_HIP(hipGetDevice(&dev));
-                INRCT_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-                m->n_cu = ncu > 0 ? ncu : 256;
-            }
-            m->n_fov = m->fov.n;
-            INRCT_REQUIRE(m->n_fov >= 1, "empty FOV");
-            m->max_k = std::min<long long>(max_k, m->n_fov);
-            if (a.kind == INRCT_HASH) {
-                hash_setup(m);
-                // sampler scratch and Adam partials, as below
-                m->flags.alloc((size_t)m->n_fov);
-                m->n_blk = cdiv(m->n_fov, 4096);
-                m->blk.alloc((size_t)(m->n_blk + 1) * sizeof(int64_t));
-                m->n_apart = (int)std::min<long long>(
-                    1024, std::max<long long>(1, cdiv(m->n_params, 2048)));
-                m->apart.alloc(sizeof(double) * m->n_apart);
-                *out = m;
-                return;
-            }
-            const int W = a.width, L = a.depth, d = a.in_dim;
-            const bool bf = a.mlp_dtype == INRCT_BF16;
-            const int kps = bf ? 16 : 2;
-            // parameter offsets
-            m->loff.assign(L + 2, 0);
-            long long off = 0;
-            for (int l = 1; l <= L + 1; ++l) {
-                m->loff[l] = off;
-                const int K = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
-                const int O = l == L + 1 ? 1 : W;
-                off += (long long)K * O + O;
-            }
-            m->n_params = off;
-            upload(m->d_loff, m->loff);
-            // fragment tables
-            std::vector<int> fl, fm, fs;
-            const int MT = W / 32;
-            const int l_first = a.kind == INRCT_FFN ? 1 : 2;
-            for (int l = l_first; l <= L; ++l) {
-                const int KS = ksteps(layer_K(a.kind, a.n_freq, d, W, l), kps);
-                m->frag_off[l] = (long long)fl.size();
-                for (int s = 0; s < KS; ++s)
-                    for (int mt = 0; mt < MT; ++mt) {
-                        fl.push_back(l);
-                        fm.push_back(mt);
-                        fs.push_back(s);
-                    }
-            }
-            m->nfrag = (long long)fl.size();
-            for (int l = 2; l <= L; ++l) {
-                const int NS = W / kps;
-                m->fragT_off[l] = (long long)fl.size() - m->nfrag;
-                for (int s = 0; s < NS; ++s)
-                    for (int mt = 0; mt < MT; ++mt) {
-                        fl.push_back(l);
-                        fm.push_back(mt);
-                        fs.push_back(s);
-                    }
-            }
-            m->nfragT = (long long)fl.size() - m->nfrag;
-            if (bf && W == 256) {
-                // chunk stream of the width-256 LDS kernel (biases excluded):
-                // layer 1 by k-step x 8 M-tiles, hidden layers by half, then
-                // k-step x 4 M-tiles
-                std::vector<int> hl, hm, hs;
-                if (a.kind == INRCT_FFN) {
-                    const int KS1 = ksteps(layer_K(a.kind, a.n_freq, d, W, 1), 16) - 1;
-                    for (int s = 0; s < KS1; ++s)
-                        for (int mt = 0; mt < 8; ++mt) {
-                            hl.push_back(1);
-                            hm.push_back(mt);
-                            hs.push_back(s);
-                        }
-                }
-                for (int l = 2; l <= L; ++l)
-                    for (int half = 0; half < 2; ++half)
-                        for (int s = 0; s < 16; ++s)
-                            for (int mt = 0; mt < 4; ++mt) {
-                                hl.push_back(l);
-                                hm.push_back(half * 4 + mt);
-                                hs.push_back(s);
-                            }
-                m->nfrag_h = (long long)hl.size();
-                upload(m->pkh_layer, hl);
-                upload(m->pkh_mt, hm);
-                upload(m->pkh_s, hs);
-                m->frag_h.alloc(m->nfrag_h * 64 * 16);
-                m->vjp_lds = a.kind == INRCT_FFN && a.n_freq % 32 == 0 &&
-                             a.n_freq <= 512 && L >= 2 && L <= kMaxDepthV;
-                if (m->vjp_lds) {
-                    // backward stream: layers L .. 2, by half, k-step x 4 M-tiles
-                    // of W_l^T (M-tiles over the inputs of layer l)
-                    std::vector<int> vl = hl, vm = hm, vs = hs;
-                    for (int l = L; l >= 2; --l)
-                        for (int half = 0; half < 2; ++half)
-                            for (int s = 0; s < 16; ++s)
-                                for (int mt = 0; mt < 4; ++mt) {
-                                    vl.push_back(l);
-                                    vm.push_back(half * 4 + mt);
-                                    vs.push_back(s);
-                                }
-                    m->nfrag_vb = (long long)vl.size() - m->nfrag_h;
-                    upload(m->pkv_layer, vl);
-                    upload(m->pkv_mt, vm);
-                    upload(m->pkv_s, vs);
-                    m->frag_v.alloc((m->nfrag_h + m->nfrag_vb) * 64 * 16);
-                }
-            }
-            upload(m->pk_layer, fl);
-            upload(m->pk_mt, fm);
-            upload(m->pk_s, fs);
-            const size_t fbytes = bf ? 16 : 4;
-            m->frag.alloc(std::max<long long>(1, m->nfrag) * 64 * fbytes);
-            m->fragT.alloc(std::max<long long>(1, m->nfragT) * 64 * fbytes);
-            // VJP scratch: chunk of P_alloc points
-            const long long kpad = cdiv(m->max_k, 256) * 256;
-            m->P_alloc = std::min<long long>(kpad, 262144);
-            m->nks = (int)cdiv(m->P_alloc, m->kslice);
-            const long long P = m->P_alloc;
-            const int K1 = layer_K(a.kind, a.n_freq, d, W, 1);
-            m->act_off[0] = 0;
-            for (int l = 1; l <= L; ++l) m->act_off[l] = (long long)K1 * P + (long long)(l - 1) * W * P;
-            m->act_elems = (long long)K1 * P + (long long)L * W * P;
-            m->dlt_elems = (long long)L * W * P + P;
-            const size_t es = bf ? 2 : 4;
-            m->act.alloc(m->act_elems * es);
-            m->mask.alloc(sizeof(uint4) * (size_t)std::max(1, L - 1) * (P / 32) * 64);
-            m->dlt.alloc(m->dlt_elems * es);
-            if (a.kind == INRCT_SIREN) {
-                for (int l = 1; l <= L; ++l) m->sig_off[l] = (long long)(l - 1) * W * P;
-                m->sig_elems = (long long)L * W * P;
-                m->sig.alloc(m->sig_elems * sizeof(float));
-            }
-            if (bf) {
-                // full-width dW tiles: layer l = 1..L+1, 256 input columns each
-                std::vector<GemmTile2> tiles2;
-                for (int l = 1; l <= L + 1; ++l) {
-                    GemmTile2 t{};
-                    t.M = l == L + 1 ? 1 : W;
-                    t.R = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
-                    t.dlt_off = (long long)(l - 1) * W * P;
-                    t.act_off = m->act_off[l - 1];
-                    t.theta_off = m->loff[l];
-                    for (int tn = 0; tn < t.R; tn += 256) {
-                        GemmTile2 u = t;
-                        u.tn = tn;
-                        u.bias = tn == 0;
-                        tiles2.push_back(u);
-                    }
-                }
-                m->ntiles = (int)tiles2.size();
-                upload(m->tiles, tiles2);
-                // split-K slices of 2048 points, shortened (to no less than
-                // 512) when the chunk is too small to give every CU a block
-                const long long want = cdiv((long long)m->n_cu, (long long)m->ntiles);
-                const long long ks = cdiv(cdiv(P, want), 256) * 256;
-                m->kslice = (int)std::min<long long>(2048, std::max<long long>(512, ks));
-                m->nks = (int)cdiv(P, m->kslice);
-                m->part.alloc((size_t)m->nks * m->ntiles * kDwPart * sizeof(float));
-            }
-            // dW GEMM tiles: layer l = 1..L+1, delta rows M, inputs R (+ bias col)
-            std::vector<GemmTile> tiles;
-            for (int l = 1; l <= L + 1; ++l) {
-                GemmTile t{};
-                t.M = l == L + 1 ? 1 : W;
-                t.R = l == L + 1 ? W : layer_K(a.kind, a.n_freq, d, W, l);
-                t.dlt_off = (long long)(l - 1) * W * P;
-                t.act_off = m->act_off[l - 1];
-                t.theta_off = m->loff[l];
-                for (int tm = 0; tm < t.M; tm += 128)
-                    for (int tn = 0; tn <= t.R; tn += 128) {
-                        GemmTile u = t;
-                        u.tm = tm;
-                        u.tn = tn;
-                        tiles.push_back(u);
-                    }
-            }
-            if (!bf) {
-                m->ntiles = (int)tiles.size();
-                upload(m->tiles, tiles);
-                m->part.alloc((size_t)m->nks * m->ntiles * 16384 * sizeof(float));
-            }
-            // sampler scratch
-            m->flags.alloc((size_t)m->n_fov);
-            m->n_blk = cdiv(m->n_fov, 4096);
-            m->blk.alloc((size_t)(m->n_blk + 1) * sizeof(int64_t));
-            // Adam partials
-            m->n_apart = (int)std::min<long long>(1024, std::max<long long>(1, cdiv(m->n_params, 2048)));
-            m->apart.alloc(sizeof(double) * m->n_apart);
+            build_in_workspace(
+                m, m->ws, ws, ws_bytes, stream, [&] { return fresh_model(arch, grid, max_k); },
+                [](inrct_model *h, Arena &ar) { build_model(h, ar); });
         } catch (...) {
             delete m;
             throw;

@@ -7,9 +7,11 @@ namespace inrct {
 constexpr int kHashMaxLevels = 32;  // hash encoding: levels per model
 constexpr int kHashMaxDepth = 4;    // hash encoding: hidden layers
 constexpr int kHashSlice = 256;     // hash VJP: points per dW partial sum
+constexpr int kAdamMaxPartials = 1024;  // Adam: float64 partials of ||g||^2
 }  // namespace inrct
 
 struct inrct_model {
+    inrct::Workspace ws;
     inr_arch arch;
     int N = 0, dim = 0;
     int n_cu = 256;  // compute units of the device the handle was created on
@@ -63,6 +65,9 @@ struct inrct_model {
 
 namespace inrct {
 // sampler / Adam / E helpers implemented in mlp.hip and step.hip
+void check_model_args(const inr_arch *arch, const inr_grid *grid, int64_t max_k);
+inrct_model *fresh_model(const inr_arch *arch, const inr_grid *grid, int64_t max_k);
+void build_model(inrct_model *m, Arena &ar);
 void model_pack(inrct_model *m, const float *theta, hipStream_t s);
 void model_eval_grid(inrct_model *m, const float *theta, const float *B, float *u,
                      hipStream_t s, bool pack = true);
@@ -73,13 +78,14 @@ void model_vjp(inrct_model *m, const float *theta, const float *B, const int32_t
                long long k, const float *v, int v_compact, double scale, float *grad,
                hipStream_t s, bool pack = true);
 // hash-encoding INR (hash.hip)
-void hash_setup(inrct_model *m);
+void hash_setup(inrct_model *m, Arena &a);
 void hash_eval(inrct_model *m, const float *theta, const int32_t *idx, long long n,
                float *out, hipStream_t s);
 void hash_vjp(inrct_model *m, const float *theta, const int32_t *idx, long long k,
               const float *v, int v_compact, double scale, float *grad, hipStream_t s);
 void model_sample(inrct_model *m, uint64_t seed, uint64_t step, long long k, int32_t *idx,
                   hipStream_t s);
+int adam_partials(long long p);
 void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float *g,
                 long long t, double lr, double b1, double b2, double eps, double *gn2,
                 hipStream_t s);

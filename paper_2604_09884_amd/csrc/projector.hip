@@ -452,62 +452,81 @@ void residual_loss(inrct_geom *geom, int loss, const float *z, const float *y,
 }
 }  // namespace inrct
 
+namespace inrct {
+// Argument checks of inrct_geom_create.
+void check_geom_args(const ct_geometry *g, const inr_grid *grid) {
+    INRCT_REQUIRE(g && grid, "null argument");
+    INRCT_REQUIRE(grid->n >= 1 && grid->n <= 4096, "grid n must be in [1, 4096]");
+    INRCT_REQUIRE(g->n_views >= 1 && g->n_u >= 1 && g->n_v >= 1, "empty detector");
+    INRCT_REQUIRE(g->angles != nullptr, "angles must be a host array");
+    INRCT_REQUIRE(g->du > 0 && g->dv > 0, "detector pitch must be positive");
+    if (g->kind == INRCT_PAR2D) {
+        INRCT_REQUIRE(grid->dim == 2, "PAR2D needs a 2D grid");
+        INRCT_REQUIRE(g->n_v == 1, "PAR2D needs n_v == 1");
+    } else if (g->kind == INRCT_FAN2D) {
+        INRCT_REQUIRE(grid->dim == 2, "FAN2D needs a 2D grid");
+        INRCT_REQUIRE(g->n_v == 1, "FAN2D needs n_v == 1");
+        // pixel segments reach sqrt(2) (1 + h) from the centre; the
+        // adjoint's bin range needs the source beyond that
+        INRCT_REQUIRE(g->sid > 1.4143 * (1.0 + 2.0 / grid->n) && g->idd > 0,
+                      "source must lie outside the image");
+    } else if (g->kind == INRCT_CONE3D) {
+        INRCT_REQUIRE(grid->dim == 3, "CONE3D needs a 3D grid");
+        INRCT_REQUIRE(g->sid > 1.8 && g->idd > 0, "source must lie outside the volume");
+        // (every ray's z slope is checked per column when the tables are built)
+        const double half_u = 0.5 * (g->n_u - 1) * g->du;
+        INRCT_REQUIRE(half_u < 0.9 * (g->sid + g->idd),
+                      "detector too wide for an in-plane principal axis");
+    } else {
+        set_error("unknown geometry kind %d", g->kind);
+        throw Error{INRCT_ENOTSUP};
+    }
+}
+
+inrct_geom *fresh_geom(const ct_geometry *g, const inr_grid *grid) {
+    inrct_geom *h = new inrct_geom();
+    h->g = *g;
+    h->N = grid->n;
+    h->dim = grid->dim;
+    h->angles.assign(g->angles, g->angles + g->n_views);
+    h->g.angles = h->angles.data();
+    return h;
+}
+
+// Tables and scratch of a geometry handle, carved from `ar`.
+void build_geom(inrct_geom *h, Arena &ar) {
+    if (h->g.kind == INRCT_PAR2D || h->g.kind == INRCT_FAN2D) {
+        std::vector<Col2D> cols;
+        std::vector<float> steps;
+        std::vector<View2D> views;
+        build_tables(h->g, h->N, cols, steps, views);
+        upload(ar, h->cols, cols);
+        upload(ar, h->steps, steps);
+        upload(ar, h->views, views);
+        h->ut.alloc(ar, sizeof(float) * (size_t)h->N * h->N);
+    } else {
+        cone_build(h, ar);
+    }
+    const int64_t m = h->m();
+    h->n_partials = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(m, 4096)));
+    h->partials.alloc(ar, sizeof(double) * h->n_partials);
+    h->q.alloc(ar, sizeof(float) * m);
+}
+}  // namespace inrct
+
 extern "C" {
 
-int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, inrct_geom **out) {
+int inrct_geom_create(const ct_geometry *g, const inr_grid *grid, void *ws, size_t ws_bytes,
+                      hipStream_t stream, inrct_geom **out) {
     return guarded([&] {
-        INRCT_REQUIRE(g && grid && out, "null argument");
+        INRCT_REQUIRE(out, "null argument");
         *out = nullptr;
-        INRCT_REQUIRE(grid->n >= 1 && grid->n <= 4096, "grid n must be in [1, 4096]");
-        INRCT_REQUIRE(g->n_views >= 1 && g->n_u >= 1 && g->n_v >= 1, "empty detector");
-        INRCT_REQUIRE(g->angles != nullptr, "angles must be a host array");
-        INRCT_REQUIRE(g->du > 0 && g->dv > 0, "detector pitch must be positive");
-        if (g->kind == INRCT_PAR2D) {
-            INRCT_REQUIRE(grid->dim == 2, "PAR2D needs a 2D grid");
-            INRCT_REQUIRE(g->n_v == 1, "PAR2D needs n_v == 1");
-        } else if (g->kind == INRCT_FAN2D) {
-            INRCT_REQUIRE(grid->dim == 2, "FAN2D needs a 2D grid");
-            INRCT_REQUIRE(g->n_v == 1, "FAN2D needs n_v == 1");
-            // pixel segments reach sqrt(2) (1 + h) from the centre; the
-            // adjoint's bin range needs the source beyond that
-            INRCT_REQUIRE(g->sid > 1.4143 * (1.0 + 2.0 / grid->n) && g->idd > 0,
-                          "source must lie outside the image");
-        } else if (g->kind == INRCT_CONE3D) {
-            INRCT_REQUIRE(grid->dim == 3, "CONE3D needs a 3D grid");
-            INRCT_REQUIRE(g->sid > 1.8 && g->idd > 0, "source must lie outside the volume");
-            // every ray must be shallower in z than in-plane
-            const double half_v = 0.5 * (g->n_v - 1) * g->dv;
-            const double half_u = 0.5 * (g->n_u - 1) * g->du;
-            const double dmin = sqrt((g->sid + g->idd) * (g->sid + g->idd));
-            INRCT_REQUIRE(half_v < 0.9 * dmin && half_u < 0.9 * dmin,
-                          "detector too large for an in-plane principal axis");
-        } else {
-            set_error("unknown geometry kind %d", g->kind);
-            throw Error{INRCT_ENOTSUP};
-        }
-        inrct_geom *h = new inrct_geom();
+        check_geom_args(g, grid);
+        inrct_geom *h = fresh_geom(g, grid);
         try {
-            h->g = *g;
-            h->N = grid->n;
-            h->dim = grid->dim;
-            h->angles.assign(g->angles, g->angles + g->n_views);
-            h->g.angles = h->angles.data();
-            if (g->kind == INRCT_PAR2D || g->kind == INRCT_FAN2D) {
-                std::vector<Col2D> cols;
-                std::vector<float> steps;
-                std::vector<View2D> views;
-                build_tables(h->g, h->N, cols, steps, views);
-                upload(h->cols, cols);
-                upload(h->steps, steps);
-                upload(h->views, views);
-                h->ut.alloc(sizeof(float) * (size_t)h->N * h->N);
-            } else {
-                cone_build(h);
-            }
-            const int64_t m = h->m();
-            h->n_partials = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(m, 4096)));
-            h->partials.alloc(sizeof(double) * h->n_partials);
-            h->q.alloc(sizeof(float) * m);
+            build_in_workspace(h, h->ws, ws, ws_bytes, stream,
+                               [&] { return fresh_geom(g, grid); },
+                               [](inrct_geom *x, Arena &ar) { build_geom(x, ar); });
         } catch (...) {
             delete h;
             throw;

@@ -213,15 +213,31 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ th, float *__r
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float *g, long long t,
-                double lr, double b1, double b2, double eps, double *gn2, hipStream_t s) {
+// Blocks of the Adam launch for p parameters: one float64 partial of ||g||^2
+// each, at most kAdamMaxPartials.
+int adam_partials(long long p) {
+    return (int)std::min<long long>(kAdamMaxPartials, std::max<long long>(1, cdiv(p, 2048)));
+}
+
+// Adam over p parameters with the partials of ||g||^2 in `partials` (at
+// least adam_partials(p) doubles).
+static void launch_adam(float *theta, float *mm, float *vv, const float *g, long long p,
+                        long long t, double lr, double b1, double b2, double eps, double *gn2,
+                        double *partials, hipStream_t s) {
     const double bc1 = 1.0 - pow(b1, (double)t);
     const double bc2 = 1.0 - pow(b2, (double)t);
-    hipLaunchKernelGGL(k_adam, dim3(m->n_apart), dim3(256), 0, s, theta, mm, vv, g, m->n_params,
-                       (float)b1, (float)b2, (float)(lr / bc1), (float)(1.0 / sqrt(bc2)),
-                       (float)eps, m->apart.as<double>());
+    const int nb = adam_partials(p);
+    hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, s, theta, mm, vv, g, p, (float)b1,
+                       (float)b2, (float)(lr / bc1), (float)(1.0 / sqrt(bc2)), (float)eps,
+                       partials);
     INRCT_CHECK_LAUNCH();
-    if (gn2) launch_sum_partials(m->apart.as<double>(), m->n_apart, gn2, s);
+    if (gn2) launch_sum_partials(partials, nb, gn2, s);
+}
+
+void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float *g, long long t,
+                double lr, double b1, double b2, double eps, double *gn2, hipStream_t s) {
+    launch_adam(theta, mm, vv, g, m->n_params, t, lr, b1, b2, eps, gn2, m->apart.as<double>(),
+                s);
 }
 
 }  // namespace inrct
@@ -230,6 +246,7 @@ void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float 
 using namespace inrct;
 
 struct inr_ctx {
+    inrct::Workspace ws;
     inrct_model *model = nullptr;
     inrct_geom *geom = nullptr;
     inrct_step_cfg cfg;
@@ -249,6 +266,32 @@ struct inr_ctx {
     }
     static const int kStages = 8;
 };
+
+namespace inrct {
+// The context's own buffers: u and v on the grid (v only at I when v_mode
+// is INRCT_V_AT_I), r on the rays, g, and I.  u outside the FOV is 0 and no
+// step writes there, so it is cleared once here.
+static void build_ctx(inr_ctx *c, long long n_grid, long long m_rays, long long n_params,
+                      Arena &ar) {
+    c->m_cap = m_rays;
+    c->u.alloc(ar, sizeof(float) * n_grid);
+    zero_fill(ar, c->u);
+    c->r.alloc(ar, sizeof(float) * m_rays);
+    c->v.alloc(ar, sizeof(float) * (c->cfg.v_mode == INRCT_V_FULL ? n_grid : c->cfg.k));
+    c->g.alloc(ar, sizeof(float) * n_params);
+    c->idx.alloc(ar, sizeof(int32_t) * c->cfg.k);
+}
+
+static void check_cfg(const inrct_step_cfg *cfg, long long max_k) {
+    INRCT_REQUIRE(cfg, "null step configuration");
+    INRCT_REQUIRE(cfg->k >= 1 && cfg->k <= max_k, "k must be in [1, max_k=%lld]", max_k);
+    INRCT_REQUIRE(cfg->loss == INRCT_LS || cfg->loss == INRCT_FLS, "unknown loss");
+    INRCT_REQUIRE(cfg->v_mode == INRCT_V_FULL || cfg->v_mode == INRCT_V_AT_I, "unknown v_mode");
+    INRCT_REQUIRE(cfg->lr > 0 && cfg->eps > 0 && cfg->beta1 >= 0 && cfg->beta1 < 1 &&
+                      cfg->beta2 >= 0 && cfg->beta2 < 1,
+                  "bad Adam hyper-parameters");
+}
+}  // namespace inrct
 
 extern "C" {
 
@@ -275,7 +318,8 @@ int inrct_adam(inrct_model *model, float *theta, float *m, float *v, const float
 }
 
 int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *cfg, float *theta,
-                   float *adam_m, float *adam_v, const float *B, const float *y, inr_ctx **out) {
+                   float *adam_m, float *adam_v, const float *B, const float *y, void *ws,
+                   size_t ws_bytes, hipStream_t stream, inr_ctx **out) {
     return guarded([&] {
         INRCT_REQUIRE(model && geom && cfg && theta && adam_m && adam_v && y && out,
                       "null argument");
@@ -283,38 +327,74 @@ int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *c
         INRCT_REQUIRE(geom_dim(geom) == model->dim && geom_N(geom) == model->N,
                       "model grid and geometry grid differ");
         INRCT_REQUIRE(model->arch.kind != INRCT_FFN || B, "FFN needs B");
-        INRCT_REQUIRE(cfg->k >= 1 && cfg->k <= model->max_k, "k must be in [1, max_k]");
-        INRCT_REQUIRE(cfg->loss == INRCT_LS || cfg->loss == INRCT_FLS, "unknown loss");
-        INRCT_REQUIRE(cfg->v_mode == INRCT_V_FULL || cfg->v_mode == INRCT_V_AT_I,
-                      "unknown v_mode");
-        INRCT_REQUIRE(cfg->lr > 0 && cfg->eps > 0 && cfg->beta1 >= 0 && cfg->beta1 < 1 &&
-                          cfg->beta2 >= 0 && cfg->beta2 < 1,
-                      "bad Adam hyper-parameters");
-        inr_ctx *c = new inr_ctx();
+        check_cfg(cfg, model->max_k);
+        auto fresh = [&] {
+            inr_ctx *c = new inr_ctx();
+            c->cfg = *cfg;
+            return c;
+        };
+        const long long ng = model->n_grid, mr = geom_rays(geom), np = model->n_params;
+        inr_ctx *c = fresh();
         try {
             c->model = model;
             c->geom = geom;
-            c->cfg = *cfg;
             c->theta = theta;
             c->am = adam_m;
             c->av = adam_v;
             c->B = B;
             c->y = y;
-            c->u.alloc(sizeof(float) * model->n_grid);
-            // u outside the FOV is 0 and no step writes there: cleared once
-            INRCT_CHECK_HIP(hipMemset(c->u.ptr, 0, c->u.bytes));
-            INRCT_CHECK_HIP(hipDeviceSynchronize());
-            c->m_cap = geom_rays(geom);
-            c->r.alloc(sizeof(float) * c->m_cap);
-            c->v.alloc(sizeof(float) * (cfg->v_mode == INRCT_V_FULL ? model->n_grid : cfg->k));
-            c->g.alloc(sizeof(float) * model->n_params);
-            c->idx.alloc(sizeof(int32_t) * cfg->k);
+            build_in_workspace(c, c->ws, ws, ws_bytes, stream, fresh,
+                               [&](inr_ctx *x, Arena &ar) { build_ctx(x, ng, mr, np, ar); });
         } catch (...) {
             delete c;
             throw;
         }
         *out = c;
     });
+}
+
+int64_t inrct_workspace_bytes(int which, const inr_arch *arch, const ct_geometry *g,
+                              const inr_grid *grid, int64_t max_k, const inrct_step_cfg *cfg) {
+    int64_t bytes = 0;
+    const int st = guarded([&] {
+        if (which == INRCT_WS_GEOM) {
+            check_geom_args(g, grid);
+            bytes = (int64_t)workspace_need<inrct_geom>(
+                [&] { return fresh_geom(g, grid); },
+                [](inrct_geom *x, Arena &ar) { build_geom(x, ar); });
+        } else if (which == INRCT_WS_MODEL || which == INRCT_WS_CTX) {
+            check_model_args(arch, grid, max_k);
+            inrct_model *tm = fresh_model(arch, grid, max_k);
+            Arena sz;
+            try {
+                build_model(tm, sz);
+            } catch (...) {
+                delete tm;
+                throw;
+            }
+            const long long ng = tm->n_grid, np = tm->n_params, kmax = tm->max_k;
+            delete tm;
+            if (which == INRCT_WS_MODEL) {
+                bytes = (int64_t)sz.used;
+                return;
+            }
+            // the context: u, r, v, g and I for this model and geometry
+            INRCT_REQUIRE(g, "null geometry");
+            check_cfg(cfg, kmax);
+            const long long mr = (long long)g->n_views * g->n_u * g->n_v;
+            bytes = (int64_t)workspace_need<inr_ctx>(
+                [&] {
+                    inr_ctx *c = new inr_ctx();
+                    c->cfg = *cfg;
+                    return c;
+                },
+                [&](inr_ctx *x, Arena &ar) { build_ctx(x, ng, mr, np, ar); });
+        } else {
+            set_error("unknown workspace kind %d", which);
+            throw Error{INRCT_EINVAL};
+        }
+    });
+    return st == INRCT_OK ? bytes : (int64_t)st;
 }
 
 int inr_ctx_destroy(inr_ctx *ctx) {

@@ -10,11 +10,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libinrct.so")
 
 INRCT_OK = 0
+INRCT_EINVAL, INRCT_ENOTSUP, INRCT_EHIP, INRCT_ENOMEM = -1, -2, -3, -4
 INRCT_PAR2D, INRCT_CONE3D, INRCT_FAN2D = 1, 2, 3
 INRCT_FFN, INRCT_SIREN, INRCT_HASH = 1, 2, 3
 INRCT_FP32, INRCT_BF16 = 0, 1
 INRCT_LS, INRCT_FLS = 0, 1
 INRCT_V_FULL, INRCT_V_AT_I = 0, 1
+INRCT_WS_GEOM, INRCT_WS_MODEL, INRCT_WS_CTX = 1, 2, 3
 
 c_void_p = ctypes.c_void_p
 c_int = ctypes.c_int
@@ -72,8 +74,12 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     P = c_void_p
     _proto(lib, "inrct_last_error", ctypes.c_char_p, [])
+    _proto(lib, "inrct_workspace_bytes", c_i64,
+           [c_int, ctypes.POINTER(InrArch), ctypes.POINTER(CtGeometry), ctypes.POINTER(InrGrid),
+            c_i64, ctypes.POINTER(StepCfg)])
     _proto(lib, "inrct_geom_create", c_int,
-           [ctypes.POINTER(CtGeometry), ctypes.POINTER(InrGrid), ctypes.POINTER(P)])
+           [ctypes.POINTER(CtGeometry), ctypes.POINTER(InrGrid), P, ctypes.c_size_t, P,
+            ctypes.POINTER(P)])
     _proto(lib, "inrct_geom_destroy", c_int, [P])
     _proto(lib, "inrct_geom_n_rays", c_i64, [P])
     _proto(lib, "ct_project", c_int, [P, P, P, P])
@@ -81,7 +87,8 @@ def load():
     _proto(lib, "ct_backproject_at", c_int, [P, P, P, c_i64, P, P])
     _proto(lib, "inrct_residual_loss", c_int, [P, c_int, P, P, P, P, P])
     _proto(lib, "inrct_model_create", c_int,
-           [ctypes.POINTER(InrArch), ctypes.POINTER(InrGrid), c_i64, ctypes.POINTER(P)])
+           [ctypes.POINTER(InrArch), ctypes.POINTER(InrGrid), c_i64, P, ctypes.c_size_t, P,
+            ctypes.POINTER(P)])
     _proto(lib, "inrct_model_destroy", c_int, [P])
     _proto(lib, "inrct_model_n_params", c_i64, [P])
     _proto(lib, "inrct_model_n_fov", c_i64, [P])
@@ -93,7 +100,8 @@ def load():
     _proto(lib, "inrct_adam", c_int,
            [P, P, P, P, P, c_i64, c_double, c_double, c_double, c_double, P, P])
     _proto(lib, "inr_ctx_create", c_int,
-           [P, P, ctypes.POINTER(StepCfg), P, P, P, P, P, ctypes.POINTER(P)])
+           [P, P, ctypes.POINTER(StepCfg), P, P, P, P, P, P, ctypes.c_size_t, P,
+            ctypes.POINTER(P)])
     _proto(lib, "inr_ctx_destroy", c_int, [P])
     _proto(lib, "inr_grad_step", c_int, [P, c_u64, P, P, P])
     _proto(lib, "inr_grad_step_views", c_int, [P, c_u64, P, P, P, P, P])
@@ -111,7 +119,7 @@ def check(status):
 
 
 EXPORTED = [
-    "inrct_last_error", "inrct_geom_create", "inrct_geom_destroy", "inrct_geom_n_rays",
+    "inrct_last_error", "inrct_workspace_bytes", "inrct_geom_create", "inrct_geom_destroy", "inrct_geom_n_rays",
     "ct_project", "ct_backproject", "ct_backproject_at", "inrct_residual_loss",
     "inrct_model_create", "inrct_model_destroy", "inrct_model_n_params",
     "inrct_model_n_fov", "inr_eval_grid", "inr_eval_points", "inr_vjp_subsampled",

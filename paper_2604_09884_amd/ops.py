@@ -36,25 +36,93 @@ def view_angles(problem: Problem) -> np.ndarray:
     return np.arange(problem.n_views, dtype=np.float64) * (problem.view_span / problem.n_views)
 
 
+def _geometry_struct(problem: Problem, angles: np.ndarray):
+    g = L.CtGeometry()
+    kinds = {"par2d": L.INRCT_PAR2D, "fan2d": L.INRCT_FAN2D, "cone3d": L.INRCT_CONE3D}
+    if problem.geometry not in kinds:
+        raise ValueError("unknown geometry %r" % problem.geometry)
+    g.kind = kinds[problem.geometry]
+    g.n_views, g.n_u, g.n_v = len(angles), problem.n_u, problem.n_v
+    g.du, g.dv, g.sid, g.idd = problem.du, problem.dv, problem.dso, problem.dod
+    g.angles = angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return g
+
+
+def _step_cfg(k, lr, seed=0, loss=L.INRCT_LS, v_mode=L.INRCT_V_FULL, beta1=0.9, beta2=0.999,
+              eps=1e-8):
+    return L.StepCfg(loss, int(k), seed, lr, beta1, beta2, eps, v_mode)
+
+
+def workspace_bytes(which, arch: INRArch | None = None, mlp_dtype: str = "fp32",
+                    problem: Problem | None = None, angles=None, dim=None, N=None, max_k=0,
+                    cfg=None) -> int:
+    """Device bytes of a handle's workspace (inrct_workspace_bytes): the
+    library's own arithmetic, run on the host."""
+    lib = L.load()
+    a = arch_struct(arch, mlp_dtype) if arch is not None else None
+    g = None
+    if problem is not None:
+        ang = np.ascontiguousarray(view_angles(problem) if angles is None
+                                   else np.asarray(angles, np.float64))
+        g = _geometry_struct(problem, ang)
+        dim = problem.dim if dim is None else dim
+        N = problem.N if N is None else N
+    grid = L.InrGrid(dim, N) if dim is not None else None
+    ref = ctypes.byref
+    nb = lib.inrct_workspace_bytes(which, ref(a) if a is not None else None,
+                                   ref(g) if g is not None else None,
+                                   ref(grid) if grid is not None else None, int(max_k),
+                                   ref(cfg) if cfg is not None else None)
+    if nb < 0:
+        L.check(int(nb))
+    return int(nb)
+
+
+def request_device_bytes(problem: Problem, mlp_dtype: str | None = None,
+                         v_mode=L.INRCT_V_FULL) -> int:
+    """Device bytes one reconstruction holds while resident: the three
+    workspaces (geometry, model, context) plus the caller's buffers theta,
+    its two Adam moments, B and y."""
+    dtype = mlp_dtype or problem.mlp_dtype
+    k = problem.k()
+    ws = (workspace_bytes(L.INRCT_WS_GEOM, problem=problem)
+          + workspace_bytes(L.INRCT_WS_MODEL, problem.arch, dtype, dim=problem.dim,
+                            N=problem.N, max_k=k)
+          + workspace_bytes(L.INRCT_WS_CTX, problem.arch, dtype, problem=problem, max_k=k,
+                            cfg=_step_cfg(k, problem.lr, v_mode=v_mode)))
+    own = 4 * (3 * problem.arch.n_params + problem.n_rays
+               + max(1, problem.arch.n_freq * problem.arch.in_dim))
+    return ws + own
+
+
+def _workspace(nbytes, device):
+    """A caller-owned device workspace (torch), 256-byte aligned."""
+    t = torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise L.InrctError("torch returned a workspace that is not 256-byte aligned")
+    return t
+
+
+def _device():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
 class Geometry:
-    """A scan geometry on a grid (inrct_geom)."""
+    """A scan geometry on a grid (inrct_geom); its tables and scratch live
+    in a torch-owned workspace."""
 
     def __init__(self, problem: Problem, angles=None):
         lib = L.load()
         self.problem = problem
         self.angles = np.ascontiguousarray(
             view_angles(problem) if angles is None else np.asarray(angles, np.float64))
-        g = L.CtGeometry()
-        kinds = {"par2d": L.INRCT_PAR2D, "fan2d": L.INRCT_FAN2D, "cone3d": L.INRCT_CONE3D}
-        if problem.geometry not in kinds:
-            raise ValueError("unknown geometry %r" % problem.geometry)
-        g.kind = kinds[problem.geometry]
-        g.n_views, g.n_u, g.n_v = len(self.angles), problem.n_u, problem.n_v
-        g.du, g.dv, g.sid, g.idd = problem.du, problem.dv, problem.dso, problem.dod
-        g.angles = self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g = _geometry_struct(problem, self.angles)
         grid = L.InrGrid(problem.dim, problem.N)
+        self.ws_bytes = workspace_bytes(L.INRCT_WS_GEOM, problem=problem, angles=self.angles)
+        self.ws = _workspace(self.ws_bytes, _device())
         h = ctypes.c_void_p()
-        L.check(lib.inrct_geom_create(ctypes.byref(g), ctypes.byref(grid), ctypes.byref(h)))
+        L.check(lib.inrct_geom_create(ctypes.byref(g), ctypes.byref(grid), _ptr(self.ws),
+                                      self.ws_bytes, _stream(), ctypes.byref(h)))
         self.handle = h
         self.n_rays = lib.inrct_geom_n_rays(h)
         self.grid_shape = (problem.N,) * problem.dim
@@ -65,6 +133,7 @@ class Geometry:
         if getattr(self, "handle", None):
             L.load().inrct_geom_destroy(self.handle)
             self.handle = None
+        self.ws = None
 
     def __del__(self):
         try:
@@ -135,9 +204,14 @@ class Model:
         grid = L.InrGrid(dim, N)
         h = ctypes.c_void_p()
         max_k = N ** dim if max_k is None else max_k
+        self.ws_bytes = workspace_bytes(L.INRCT_WS_MODEL, arch, mlp_dtype, dim=dim, N=N,
+                                        max_k=max_k)
+        self.ws = _workspace(self.ws_bytes, _device())
         L.check(lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), int(max_k),
+                                       _ptr(self.ws), self.ws_bytes, _stream(),
                                        ctypes.byref(h)))
         self.handle = h
+        self.max_k = int(max_k)
         self.n_params = lib.inrct_model_n_params(h)
         self.n_fov = lib.inrct_model_n_fov(h)
         self.grid_shape = (N,) * dim
@@ -151,6 +225,7 @@ class Model:
         if getattr(self, "handle", None):
             L.load().inrct_model_destroy(self.handle)
             self.handle = None
+        self.ws = None
 
     def __del__(self):
         try:
@@ -223,15 +298,21 @@ class GradStepper:
         self.m = torch.zeros_like(theta)
         self.v = torch.zeros_like(theta)
         self.k = int(k)
-        cfg = L.StepCfg(loss, self.k, seed, lr, beta1, beta2, eps, v_mode)
+        cfg = _step_cfg(self.k, lr, seed, loss, v_mode, beta1, beta2, eps)
+        p = geom.problem
+        self.ws_bytes = workspace_bytes(L.INRCT_WS_CTX, model.arch, model.mlp_dtype,
+                                        problem=p, angles=geom.angles, dim=model.dim,
+                                        N=model.N, max_k=model.max_k, cfg=cfg)
+        self.ws = _workspace(self.ws_bytes, theta.device)
         h = ctypes.c_void_p()
         L.check(lib.inr_ctx_create(model.handle, geom.handle, ctypes.byref(cfg), _ptr(theta),
                                    _ptr(self.m), _ptr(self.v), _ptr(B), _ptr(y),
-                                   ctypes.byref(h)))
+                                   _ptr(self.ws), self.ws_bytes, _stream(), ctypes.byref(h)))
         self.handle = h
         dev = theta.device
-        self.loss = torch.zeros((), dtype=torch.float64, device=dev)
-        self.gnorm2 = torch.zeros((), dtype=torch.float64, device=dev)
+        # the step's loss and ||g||^2 side by side, so one copy reads both
+        self.stats = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.loss, self.gnorm2 = self.stats[0], self.stats[1]
 
     def step(self, t: int):
         """Runs step t (0-based); loss and ||g||^2 land in self.loss /
@@ -269,6 +350,7 @@ class GradStepper:
         if getattr(self, "handle", None):
             L.load().inr_ctx_destroy(self.handle)
             self.handle = None
+        self.ws = None
 
     def __del__(self):
         try:

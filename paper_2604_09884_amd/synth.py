@@ -112,18 +112,27 @@ def chord_integrals(ph, dim: int, p0: np.ndarray, d: np.ndarray) -> np.ndarray:
     d = np.asarray(d, np.float64)
     out = np.zeros(p0.shape[0])
     dn = np.linalg.norm(d, axis=1)
+    dh = d / dn[:, None]
     rots = _rotations(ph, dim)
     for cen, ax, R, mu in zip(ph["centre"], ph["axes"], rots, ph["mu"]):
-        q0 = ((p0 - cen) @ R) / ax
-        qd = (d @ R) / ax
+        # only rays passing within the largest semi-axis of the centre can
+        # meet the shape (it lies inside that ball)
+        w = cen - p0
+        wd = np.einsum("ij,ij->i", w, dh)
+        near = np.einsum("ij,ij->i", w, w) - wd * wd <= (1.0 + 1e-9) * float(np.max(ax)) ** 2
+        sel = np.nonzero(near)[0]
+        if sel.size == 0:
+            continue
+        q0 = ((p0[sel] - cen) @ R) / ax
+        qd = (d[sel] @ R) / ax
         a = np.einsum("ij,ij->i", qd, qd)
         b = 2 * np.einsum("ij,ij->i", q0, qd)
         c0 = np.einsum("ij,ij->i", q0, q0) - 1
         disc = b * b - 4 * a * c0
         ok = disc > 0
         chord = np.zeros_like(a)
-        chord[ok] = np.sqrt(disc[ok]) / a[ok] * dn[ok]
-        out += mu * chord
+        chord[ok] = np.sqrt(disc[ok]) / a[ok] * dn[sel][ok]
+        out[sel] += mu * chord
     return out
 
 

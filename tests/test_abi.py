@@ -37,7 +37,8 @@ def test_errors_are_reported_without_a_gpu():
     h = ctypes.c_void_p()
     grid = L.InrGrid(2, 0)
     a = L.InrArch(1, 2, 8, 128, 2, 30.0, 0)
-    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, None, 0, None,
+                                ctypes.byref(h))
     assert rc == -1
     assert b"grid n" in lib.inrct_last_error()
 
@@ -57,11 +58,13 @@ def test_hash_arch_is_checked_before_any_device_call():
     grid = L.InrGrid(2, 16)
     # width 128 is not a hash-INR width
     a = L.InrArch(L.INRCT_HASH, 2, 0, 128, 2, 30.0, L.INRCT_FP32, 4, 10, 4, 16)
-    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, None, 0, None,
+                                ctypes.byref(h))
     assert rc != 0 and b"width" in lib.inrct_last_error()
     # BF16 is refused for the hash INR
     a = L.InrArch(L.INRCT_HASH, 2, 0, 64, 2, 30.0, L.INRCT_BF16, 4, 10, 4, 16)
-    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, ctypes.byref(h))
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), 10, None, 0, None,
+                                ctypes.byref(h))
     assert rc != 0 and b"FP32" in lib.inrct_last_error()
 
 
@@ -76,10 +79,74 @@ def test_fan_geometry_checks_on_the_host():
         g.kind, g.n_views, g.n_u, g.n_v = L.INRCT_FAN2D, 4, n_u, n_v
         g.du, g.dv, g.sid, g.idd = du, du, sid, idd
         g.angles = ctypes.cast(angles, ctypes.POINTER(ctypes.c_double))
-        return lib.inrct_geom_create(ctypes.byref(g), ctypes.byref(grid), ctypes.byref(h))
+        return lib.inrct_geom_create(ctypes.byref(g), ctypes.byref(grid), None, 0, None,
+                                     ctypes.byref(h))
 
     assert make(64, 0.05, 1.2, 1.0) != 0          # source inside the image
     assert b"outside" in lib.inrct_last_error()
     assert make(64, 0.05, 3.0, 1.0, n_v=2) != 0   # a fan has one detector row
     assert make(101, 1.0, 3.0, 1.0) != 0          # a fan wider than 90 degrees
     assert b"90" in lib.inrct_last_error()
+
+
+def _cone(lib, n_v, dv, N=32, n_u=48, V=4):
+    angles = (ctypes.c_double * V)(*[2 * 3.141592653589793 * j / V for j in range(V)])
+    g = L.CtGeometry()
+    g.kind, g.n_views, g.n_u, g.n_v = L.INRCT_CONE3D, V, n_u, n_v
+    g.du, g.dv, g.sid, g.idd = 3.1 / n_u, dv, 31.25, 15.625
+    g.angles = ctypes.cast(angles, ctypes.POINTER(ctypes.c_double))
+    return g, angles, L.InrGrid(3, N)
+
+
+def test_cone_geometry_rejects_rows_steeper_than_the_principal_axis():
+    # the detector half-height must stay below every column's in-plane
+    # principal component |d_axis|; at a 45 degree view that is about
+    # (D_so + D_od) / sqrt(2) = 33.1, so a half-height of 36 (0.77 of
+    # D_so + D_od) is refused although it is below 0.9 (D_so + D_od)
+    lib = L.load()
+    h = ctypes.c_void_p()
+    g, keep, grid = _cone(lib, 2, 72.0, V=8)
+    rc = lib.inrct_geom_create(ctypes.byref(g), ctypes.byref(grid), None, 0, None,
+                               ctypes.byref(h))
+    assert rc == L.INRCT_OK - 1 and b"steeper" in lib.inrct_last_error()
+    # the same check runs when only the workspace is sized
+    assert lib.inrct_workspace_bytes(L.INRCT_WS_GEOM, None, ctypes.byref(g),
+                                     ctypes.byref(grid), 0, None) == -1
+    g2, keep2, grid2 = _cone(lib, 2, 1.0, V=8)
+    assert lib.inrct_workspace_bytes(L.INRCT_WS_GEOM, None, ctypes.byref(g2),
+                                     ctypes.byref(grid2), 0, None) > 0
+
+
+def test_workspace_bytes_on_the_host():
+    # inrct_workspace_bytes runs the handles' build code in a counting mode:
+    # no device is needed, the answer is repeatable, grows with the problem,
+    # and the argument checks of the create calls apply
+    lib = L.load()
+    ref = ctypes.byref
+    a = L.InrArch(L.INRCT_FFN, 3, 256, 256, 5, 30.0, L.INRCT_BF16)
+    g, keep, grid = _cone(lib, 48, 3.1 / 48)
+    cfg = L.StepCfg(L.INRCT_LS, 300, 0, 1e-3, 0.9, 0.999, 1e-8, L.INRCT_V_FULL)
+    wg = lib.inrct_workspace_bytes(L.INRCT_WS_GEOM, None, ref(g), ref(grid), 0, None)
+    wm = lib.inrct_workspace_bytes(L.INRCT_WS_MODEL, ref(a), None, ref(grid), 300, None)
+    wc = lib.inrct_workspace_bytes(L.INRCT_WS_CTX, ref(a), ref(g), ref(grid), 300, ref(cfg))
+    assert wg > 0 and wm > 0 and wc > 0
+    assert wm == lib.inrct_workspace_bytes(L.INRCT_WS_MODEL, ref(a), None, ref(grid), 300, None)
+    # the context holds u, r, v on the grid or rays, g and I (each 256-byte aligned)
+    n_grid, m = 32 ** 3, 4 * 48 * 48
+    lo = 4 * (2 * n_grid + m + 394753) + 4 * 300
+    assert lo <= wc <= lo + 5 * 256
+    # v only at I is smaller
+    cfg_i = L.StepCfg(L.INRCT_LS, 300, 0, 1e-3, 0.9, 0.999, 1e-8, L.INRCT_V_AT_I)
+    assert lib.inrct_workspace_bytes(L.INRCT_WS_CTX, ref(a), ref(g), ref(grid), 300,
+                                     ref(cfg_i)) == wc - 4 * (n_grid - 300) - \
+        ((4 * n_grid + 255) // 256 * 256 - 4 * n_grid) + ((4 * 300 + 255) // 256 * 256 - 4 * 300)
+    # a larger max_k needs more VJP scratch
+    assert lib.inrct_workspace_bytes(L.INRCT_WS_MODEL, ref(a), None, ref(grid), 3000,
+                                     None) > wm
+    # k above max_k, unknown kinds and bad arguments are errors
+    cfg_big = L.StepCfg(L.INRCT_LS, 301, 0, 1e-3, 0.9, 0.999, 1e-8, L.INRCT_V_FULL)
+    assert lib.inrct_workspace_bytes(L.INRCT_WS_CTX, ref(a), ref(g), ref(grid), 300,
+                                     ref(cfg_big)) == -1
+    assert lib.inrct_workspace_bytes(7, None, None, None, 0, None) == -1
+    bad = L.InrGrid(3, 0)
+    assert lib.inrct_workspace_bytes(L.INRCT_WS_MODEL, ref(a), None, ref(bad), 300, None) == -1

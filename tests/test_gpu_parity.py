@@ -151,34 +151,6 @@ def test_eval_and_vjp_match_oracle(name, arch, prob, dtype):
         assert rel(g, g_ref) <= 1e-4
 
 
-def test_vjp_multi_chunk_c4_arch():
-    # k above one 65536-point chunk: cross-chunk accumulation of the partials
-    ops = _ops()
-    arch = configs.C4.arch
-    N = 64
-    fov = ogrid.fov_indices(3, N)
-    theta, B = synth.random_theta(arch, 17)
-    cand = np.sort(RNG(18).choice(fov, size=120000, replace=False))
-    idx = cand[_away_from_kinks(theta, B, arch, ogrid.coords(3, N, cand), 2e-4)]
-    k = idx.size
-    assert k > 65536 + 1000
-    m = ops.Model(arch, 3, N, "fp32", max_k=k)
-    v = RNG(19).standard_normal(k)
-    g = host(ops.inr_vjp_subsampled(m, dev(theta), dev(B.ravel()), dev(idx, torch.int32),
-                                    dev(v), 1.5, v_compact=True))
-    g_ref = oinr.vjp(theta, B, ogrid.coords(3, N, idx), 1.5 * v, arch)
-    e = rel(g, g_ref)
-    say("multi-chunk g rel", e, "k", k)
-    assert e <= 1e-4
-    # linearity across chunks: the sum over I equals the sum of the halves
-    h = k // 2
-    ga = host(ops.inr_vjp_subsampled(m, dev(theta), dev(B.ravel()), dev(idx[:h], torch.int32),
-                                     dev(v[:h]), 1.5, v_compact=True))
-    gb = host(ops.inr_vjp_subsampled(m, dev(theta), dev(B.ravel()), dev(idx[h:], torch.int32),
-                                     dev(v[h:]), 1.5, v_compact=True))
-    assert rel(ga + gb, g) <= 1e-5
-
-
 @pytest.mark.parametrize("n_N,k", [((2, 16), 1), ((2, 45), 700), ((3, 40), 20000)])
 def test_sampler_matches_oracle(n_N, k):
     ops = _ops()

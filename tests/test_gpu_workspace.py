@@ -1,0 +1,124 @@
+"""Device memory of the handles: inrct_workspace_bytes is exactly what a
+create call takes; a create on a torch-owned workspace allocates nothing
+and gives the same results as one on a library-owned workspace; a short
+workspace is refused."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_09884_amd import configs, synth
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    return [
+        ("c1-ffn128-fp32", configs.C1, "fp32"),
+        ("cone-ffn256-bf16", configs.cone_problem(40, 6, 48, arch=configs.C4.arch,
+                                                  k_frac=0.05), "bf16"),
+        ("siren-bf16", configs.par2d_problem(96, 20, 137, arch=configs.C2.arch,
+                                             k_frac=1 / 16), "bf16"),
+        ("hash-fp32", configs.C7.with_(N=64, n_views=30, n_u=91, du=3.1 / 91,
+                                       dv=3.1 / 91), "fp32"),
+    ]
+
+
+def _free():
+    torch.cuda.synchronize()
+    return torch.cuda.mem_get_info()[0]
+
+
+@pytest.mark.parametrize("name,p,dtype", _cases(), ids=[c[0] for c in _cases()])
+def test_workspace_bytes_are_what_create_allocates(name, p, dtype):
+    from paper_2604_09884_amd import lib as L
+    from paper_2604_09884_amd import ops
+    lib = L.load()
+    say("case", name)
+    k = p.k()
+    a = ops.arch_struct(p.arch, dtype)
+    grid = L.InrGrid(p.dim, p.N)
+    nb = ops.workspace_bytes(L.INRCT_WS_MODEL, p.arch, dtype, dim=p.dim, N=p.N, max_k=k)
+    # library-owned workspace: the device's free memory drops by that much
+    # (up to the allocator's page rounding)
+    h = ctypes.c_void_p()
+    f0 = _free()
+    L.check(lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), k, None, 0, None,
+                                   ctypes.byref(h)))
+    f1 = _free()
+    say(name, "model workspace %d B, device free memory delta %d B" % (nb, f0 - f1))
+    assert (nb if nb >= (2 << 20) else 0) <= f0 - f1 <= nb + (4 << 20)
+    lib.inrct_model_destroy(h)
+    # a workspace one byte short is refused, before anything is enqueued
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), k,
+                                ctypes.c_void_p(ws.data_ptr()), nb - 1, None, ctypes.byref(h))
+    assert rc == L.INRCT_EINVAL and b"too small" in lib.inrct_last_error()
+    # a caller-owned workspace: the create allocates nothing
+    f2 = _free()
+    rc = lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), k,
+                                ctypes.c_void_p(ws.data_ptr()), nb, None, ctypes.byref(h))
+    L.check(rc)
+    assert _free() == f2
+    lib.inrct_model_destroy(h)
+    # geometry handle: the same
+    ng = ops.workspace_bytes(L.INRCT_WS_GEOM, problem=p)
+    f0 = _free()
+    g = ops.view_angles(p)
+    gs = ops._geometry_struct(p, np.ascontiguousarray(g))
+    hg = ctypes.c_void_p()
+    L.check(lib.inrct_geom_create(ctypes.byref(gs), ctypes.byref(grid), None, 0, None,
+                                  ctypes.byref(hg)))
+    f1 = _free()
+    say(name, "geometry workspace %d B, delta %d B" % (ng, f0 - f1))
+    # (HIP packs allocations under its 2 MiB page into pages it already holds)
+    assert (ng if ng >= (2 << 20) else 0) <= f0 - f1 <= ng + (4 << 20)
+    lib.inrct_geom_destroy(hg)
+
+
+def test_torch_workspaces_give_the_library_owned_results():
+    # one C1 step on torch-owned workspaces (ops) and on library-owned ones
+    # (C ABI with ws = NULL): identical loss and gradient
+    from paper_2604_09884_amd import lib as L
+    from paper_2604_09884_amd import ops
+    lib = L.load()
+    p = configs.C1
+    theta, B = synth.init_inr(p.arch, p.seed_init)
+    y = dev(synth.sinogram(p).astype(np.float32).ravel())
+    m = ops.Model(p.arch, p.dim, p.N, "fp32", max_k=p.k())
+    g = ops.Geometry(p)
+    st = ops.GradStepper(m, g, dev(theta), dev(B.ravel()), y, p.k(), p.lr, seed=p.seed_sampler)
+    st.step(0)
+    g_torch = host(st.buffer(3, m.n_params))
+    # the same step with every workspace allocated by the library
+    a = ops.arch_struct(p.arch, "fp32")
+    grid = L.InrGrid(p.dim, p.N)
+    hm, hg, hc = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    L.check(lib.inrct_model_create(ctypes.byref(a), ctypes.byref(grid), p.k(), None, 0, None,
+                                   ctypes.byref(hm)))
+    ang = np.ascontiguousarray(ops.view_angles(p))
+    gs = ops._geometry_struct(p, ang)
+    L.check(lib.inrct_geom_create(ctypes.byref(gs), ctypes.byref(grid), None, 0, None,
+                                  ctypes.byref(hg)))
+    th2, Bd = dev(theta), dev(B.ravel())
+    mm, vv = torch.zeros_like(th2), torch.zeros_like(th2)
+    cfg = ops._step_cfg(p.k(), p.lr, p.seed_sampler)
+    L.check(lib.inr_ctx_create(hm, hg, ctypes.byref(cfg), ctypes.c_void_p(th2.data_ptr()),
+                               ctypes.c_void_p(mm.data_ptr()), ctypes.c_void_p(vv.data_ptr()),
+                               ctypes.c_void_p(Bd.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                               None, 0, None, ctypes.byref(hc)))
+    stats = torch.zeros(2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    L.check(lib.inr_grad_step(hc, 0, ctypes.c_void_p(stats.data_ptr()),
+                              ctypes.c_void_p(stats.data_ptr() + 8), None))
+    torch.cuda.synchronize()
+    g_lib = host(ops._wrap_device(lib.inr_ctx_buffer(hc, 3), m.n_params, torch.float32,
+                                  th2.device))
+    assert np.array_equal(g_torch, g_lib)
+    assert host(st.stats)[0] == host(stats)[0]
+    assert np.array_equal(host(st.theta), host(th2))
+    for f, h in ((lib.inr_ctx_destroy, hc), (lib.inrct_geom_destroy, hg),
+                 (lib.inrct_model_destroy, hm)):
+        f(h)

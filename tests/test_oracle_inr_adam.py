@@ -37,6 +37,30 @@ def test_forward_hand_computed():
     assert abs(inr.forward(theta, B, x, arch)[0] - ref) < 1e-15
 
 
+def test_siren_forward_hand_computed():
+    # SIREN with width 2, two sine layers and omega0 = 2.5, written out by
+    # hand: a_l = sin(omega0 (W_l a_{l-1} + b_l)), f = w . a_2 + b
+    arch = configs.INRArch("siren", 2, 0, 0.0, 2, 2, omega0=2.5)
+    W1 = np.array([[0.7, -0.3], [0.2, 0.9]])
+    b1 = np.array([0.05, -0.1])
+    W2 = np.array([[-0.4, 0.6], [1.1, 0.25]])
+    b2 = np.array([0.2, 0.0])
+    w3 = np.array([[1.5, -0.8]])
+    b3 = np.array([-0.25])
+    theta = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3.ravel(), b3])
+    x0, x1 = -0.3, 0.6
+    h0 = math.sin(2.5 * (0.7 * x0 - 0.3 * x1 + 0.05))
+    h1 = math.sin(2.5 * (0.2 * x0 + 0.9 * x1 - 0.1))
+    g0 = math.sin(2.5 * (-0.4 * h0 + 0.6 * h1 + 0.2))
+    g1 = math.sin(2.5 * (1.1 * h0 + 0.25 * h1))
+    ref = 1.5 * g0 - 0.8 * g1 - 0.25
+    out = inr.forward(theta, np.zeros((0, 2)), np.array([[x0, x1]]), arch)
+    assert abs(out[0] - ref) < 1e-15
+    # the same value with omega0 = 1 differs: the factor is applied per layer
+    arch1 = configs.INRArch("siren", 2, 0, 0.0, 2, 2, omega0=1.0)
+    assert abs(inr.forward(theta, None, np.array([[x0, x1]]), arch1)[0] - ref) > 1e-2
+
+
 def test_param_counts_of_workloads():
     assert inr.n_params(configs.C1.arch) == 49665
     assert inr.n_params(configs.C2.arch) == 264193

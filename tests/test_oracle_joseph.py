@@ -295,3 +295,43 @@ def test_fan_large_distance_approaches_parallel():
         pq, dq = geometry.par2d_rays(1, K, du, span=th, views=[1])
         zq = joseph.project(u, N, 2, pq, dq)
         assert np.abs(zq - zf[j]).max() <= 1e-5 * np.abs(zq).max()
+
+
+# ------------------------------------------------------------ 3D cone beam
+def test_cone_rays_geometry():
+    # Every ray starts at the source, on the circle of radius D_so in the
+    # plane z = 0; its end point Q lies in the detector plane, D_od on the far
+    # side of the rotation axis; neighbouring columns are du apart along
+    # e_u = (-sin, cos, 0) and neighbouring rows dv apart along +z; the
+    # middle pixel of an odd detector lies on the line through the source and
+    # the origin; rays are ordered [view][row][column]; the generator behind
+    # the data agrees.
+    V, nu, nv = 5, 9, 7
+    du, dv, dso, dod = 0.05, 0.08, 31.25, 15.625
+    p0, d = geometry.cone3d_rays(V, nu, nv, du, dv, dso, dod)
+    assert p0.shape == (V * nv * nu, 3)
+    assert np.allclose(np.linalg.norm(p0[:, :2], axis=1), dso, rtol=1e-14)
+    assert np.all(p0[:, 2] == 0.0)
+    ph = np.repeat(np.arange(V) * (2 * np.pi / V), nv * nu)
+    n = np.stack([np.cos(ph), np.sin(ph), 0 * ph], 1)
+    Q = p0 + d
+    assert np.allclose(np.einsum("ij,ij->i", Q, n), -dod, atol=1e-12)
+    Qg = Q.reshape(V, nv, nu, 3)
+    eu = np.stack([-np.sin(ph), np.cos(ph), 0 * ph], 1).reshape(V, nv, nu, 3)
+    du_step = np.einsum("vbai,vbai->vba", np.diff(Qg, axis=2), eu[:, :, 1:])
+    assert np.allclose(du_step, du, rtol=1e-10)
+    assert np.allclose(np.diff(Qg, axis=2)[..., 2], 0.0, atol=1e-14)
+    assert np.allclose(np.diff(Qg, axis=1)[..., 2], dv, rtol=1e-10)
+    assert np.allclose(np.diff(Qg, axis=1)[..., :2], 0.0, atol=1e-13)
+    # central ray: source, origin and middle pixel are collinear
+    mid = (np.arange(V) * nv + nv // 2) * nu + nu // 2
+    assert np.abs(np.cross(p0[mid], d[mid])).max() <= 1e-12 * dso * (dso + dod)
+    assert np.allclose(Q[mid], -dod * n[mid], atol=1e-12)
+    # hand-derived pixel: view 1 of 4 (phi = 90 deg), row 0, column nu - 1
+    p1, d1 = geometry.cone3d_rays(4, nu, nv, du, dv, dso, dod, views=[1], rows=[0],
+                                  cols=[nu - 1])
+    ua, vb = (nu - 1) / 2 * du, -(nv - 1) / 2 * dv
+    assert np.allclose(p1[0], [0.0, dso, 0.0], atol=1e-13)
+    assert np.allclose(p1[0] + d1[0], [-ua, -dod, vb], atol=1e-13)
+    sp0, sd = synth.rays_cone3d(V, nu, nv, du, dv, dso, dod)
+    assert np.allclose(sp0, p0, atol=1e-13) and np.allclose(sd, d, atol=1e-13)

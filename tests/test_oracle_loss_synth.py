@@ -4,7 +4,7 @@ import math
 
 import numpy as np
 
-from oracle import loss
+from oracle import loss, step
 from paper_2604_09884_amd import synth
 
 
@@ -74,3 +74,14 @@ def test_phantoms_inside_fov():
         assert np.all(np.linalg.norm(e["centre"], axis=1) + e["axes"].max(1) <= 0.95)
         s = synth.random_ellipsoids(20, seed)
         assert np.all(np.linalg.norm(s["centre"], axis=1) + s["axes"].max(1) <= 0.95)
+
+
+def test_mse_hand_computed():
+    # mean of squared differences over the FOV points only (Sec. IV): FOV =
+    # grid indices 0, 2, 3 of a 2 x 2 image; index 1 lies outside and its
+    # large difference must not count
+    u = np.array([[1.0, 2.0], [3.0, 4.0]])
+    ref = np.array([[0.0, 100.0], [5.0, 4.5]])
+    fov = np.array([0, 2, 3])
+    assert step.mse(u, ref, fov) == (1.0 + 4.0 + 0.25) / 3
+    assert step.mse(ref, ref, fov) == 0.0
