@@ -265,6 +265,24 @@ int inrct_adam(inrct_model *model, float *theta, float *m, float *v,
                double beta2, double eps, double *gnorm2_out,
                hipStream_t stream);
 
+/* Adam as inrct_adam (same kernels, bitwise the same theta, m, v and
+ * ||g||^2), without a model handle or workspace, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The float64 partials of ||g||^2
+ * live in a static device array of 1024 doubles (8 KB) that each GPU the
+ * library runs on keeps until the process ends; its address is looked up
+ * once per device on the first call there.  p: parameters, 1 <=
+ * p <= INRCT_ADAM_NOALLOC_MAX_P (any p needs at most those 1024 partials);
+ * a larger p is refused with INRCT_EINVAL.  Every partial the reduction
+ * reads is written by the same call first, so nothing carries over between
+ * calls; but calls that overlap on one device (different streams, or
+ * different threads) share the array and race.  Allocates nothing. */
+#define INRCT_ADAM_NOALLOC_MAX_P 2147483647LL
+int inrct_adam_noalloc(float *theta, float *m, float *v, const float *g,
+                       int64_t p, int64_t t, double lr, double beta1,
+                       double beta2, double eps, double *gnorm2_out,
+                       hipStream_t stream);
+
 /* ------------------------------------------------------------ full step */
 struct inrct_step_cfg {
     int loss;               /* INRCT_LS or INRCT_FLS                        */

@@ -7,6 +7,9 @@
 // in rank order with a fixed-order scan, giving sorted grid indices.
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 #include "model.h"
 
 namespace inrct {
@@ -240,6 +243,29 @@ void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float 
                 s);
 }
 
+// ---------------------------------------------- Adam without allocation
+// The float64 partials of inrct_adam_noalloc live in this file-scope device
+// array (each device the library runs on holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: the
+// name is a host-side stand-in, not a device address.  The address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) double scratch[kAdamMaxPartials];
+
+static double *scratch_ptr() {
+    static std::mutex mu;
+    static std::map<int, double *> ptrs;
+    int dev = 0;
+    INRCT_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) return it->second;
+    void *p = nullptr;
+    INRCT_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    INRCT_REQUIRE(p != nullptr, "no device address for the Adam scratch array");
+    ptrs[dev] = (double *)p;
+    return (double *)p;
+}
+
 }  // namespace inrct
 
 // ==================================================================== ABI
@@ -314,6 +340,24 @@ int inrct_adam(inrct_model *model, float *theta, float *m, float *v, const float
         INRCT_REQUIRE(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && lr > 0,
                       "bad Adam hyper-parameters");
         model_adam(model, theta, m, v, g, t, lr, beta1, beta2, eps, gnorm2_out, stream);
+    });
+}
+
+int inrct_adam_noalloc(float *theta, float *m, float *v, const float *g, int64_t p, int64_t t,
+                       double lr, double beta1, double beta2, double eps, double *gnorm2_out,
+                       hipStream_t stream) {
+    return guarded([&] {
+        INRCT_REQUIRE(theta && m && v && g, "null argument");
+        INRCT_REQUIRE(p >= 1 && p <= INRCT_ADAM_NOALLOC_MAX_P,
+                      "p = %lld outside [1, %lld] (the partials array holds %d entries)",
+                      (long long)p, (long long)INRCT_ADAM_NOALLOC_MAX_P, kAdamMaxPartials);
+        INRCT_REQUIRE(t >= 1, "t is 1-based");
+        INRCT_REQUIRE(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && lr > 0,
+                      "bad Adam hyper-parameters");
+        // every partial the reduction reads is written by the Adam launch
+        // first, so nothing needs clearing between calls
+        launch_adam(theta, m, v, g, p, t, lr, beta1, beta2, eps, gnorm2_out, scratch_ptr(),
+                    stream);
     });
 }
 

@@ -99,6 +99,8 @@ def load():
     _proto(lib, "inrct_sample", c_int, [P, c_u64, c_u64, c_i64, P, P])
     _proto(lib, "inrct_adam", c_int,
            [P, P, P, P, P, c_i64, c_double, c_double, c_double, c_double, P, P])
+    _proto(lib, "inrct_adam_noalloc", c_int,
+           [P, P, P, P, c_i64, c_i64, c_double, c_double, c_double, c_double, P, P])
     _proto(lib, "inr_ctx_create", c_int,
            [P, P, ctypes.POINTER(StepCfg), P, P, P, P, P, P, ctypes.c_size_t, P,
             ctypes.POINTER(P)])
@@ -123,6 +125,6 @@ EXPORTED = [
     "ct_project", "ct_backproject", "ct_backproject_at", "inrct_residual_loss",
     "inrct_model_create", "inrct_model_destroy", "inrct_model_n_params",
     "inrct_model_n_fov", "inr_eval_grid", "inr_eval_points", "inr_vjp_subsampled",
-    "inrct_sample", "inrct_adam", "inr_ctx_create", "inr_ctx_destroy", "inr_grad_step",
+    "inrct_sample", "inrct_adam", "inrct_adam_noalloc", "inr_ctx_create", "inr_ctx_destroy", "inr_grad_step",
     "inr_grad_step_views", "inr_ctx_buffer", "inr_ctx_enable_timing", "inr_ctx_stage_ms",
 ]
