@@ -101,7 +101,7 @@ typedef struct {
  *        (k - (n_u-1)/2) du; n_v must be 1.
  * CONE3D: source sid (cos, sin, 0), detector centre -idd (cos, sin, 0),
  *        detector axes (-sin, cos, 0) and (0, 0, 1); pixel (a, b) at
- *        ((a - (n_u-1)/2) du, (b - (n_v-1)/2) dv); grids up to n = 1286.
+ *        ((a - (n_u-1)/2) du, (b - (n_v-1)/2) dv); grids up to n = 1290.
  * FAN2D: the in-plane part of CONE3D: source sid (cos, sin), detector
  *        centre -idd (cos, sin), detector axis (-sin, cos), bin a at
  *        (a - (n_u-1)/2) du; n_v must be 1 and sid > 1.4143 (1 + 2/n)

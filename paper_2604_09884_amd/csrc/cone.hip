@@ -9,15 +9,13 @@
 // exactly the interpolation weights P applies, and neither does float64
 // work per sample.
 //
-// P: one ray per lane, a wave an 8 x 8 patch of (column, row) rays and a
-// workgroup 16 x 16, slices visited in
-// order.  Rays whose principal axis is x read a transposed copy of the
-// volume ([z][x][y]) so that neighbouring lanes read neighbouring addresses
-// in both cases.
-// P^T: one thread per (x, y) voxel column segment of kZc voxels; for each
-// view, the detector columns whose stencil covers the voxel in-plane are
-// found once per segment, then a monotone sweep over detector rows gathers
-// the step-weighted residual for the kZc voxels.  No atomics.
+// P: a workgroup integrates a tile of 64 x 32 rays of one view, slice chunk
+// by slice chunk, from the chunk's footprint of u staged in LDS.
+// P^T: one thread per (x, y) voxel column segment of kZc voxels; view by
+// view the block's detector footprint is staged in LDS; the detector
+// columns whose stencil covers the voxel in-plane are found once per
+// segment, then a monotone sweep over detector rows gathers the
+// step-weighted residual for the kZc voxels.  No atomics.
 #include <math.h>
 
 #include "geom.h"
@@ -25,8 +23,133 @@
 namespace inrct {
 
 static const double kFix40 = 1099511627776.0;  // 2^40
-static const int kPad = 2;  // zero border of the padded volume copies
-static const unsigned kConeFwdLdsCap = 54 * 1024;  // occupancy cap of k_cone_fwd
+
+// LDS footprint of one chunk of a projector tile: at most kFootO positions
+// along the ray's non-principal in-plane axis and kFootZ along z.  Two
+// layouts (floats):
+//   y-principal rays, [s][z][o]: o stride 1, z stride kLdsZY, s stride
+//     kFootZ kLdsZY (rows padded to 65 so neighbouring z rows fall in
+//     neighbouring banks);
+//   x-principal rays, [o][z][s]: s stride 1, z stride kLdsZX, o stride
+//     kLdsOX (odd, so lanes at neighbouring o hit neighbouring banks);
+// each matching the direction in which u ([z][y][x]) is contiguous.
+constexpr int kFootO = 80, kFootZ = 24;
+// The adjoint: voxels per thread along z, and the LDS footprint caps
+// (detector columns and rows per view and block) with the staged row stride
+constexpr int kZc = 16;
+constexpr int kBpA = 64, kBpB = 48, kBpRs = kBpA + 1;
+constexpr int kLdsZY = kFootO + 1, kLdsSY = kFootZ * kLdsZY;
+constexpr int kLdsZX = kTileS, kLdsOX = kFootZ * kLdsZX + 1;
+constexpr int kLdsFloatsY = kTileS * kLdsSY, kLdsFloatsX = kFootO * kLdsOX;
+
+__host__ __device__ inline int fx40_floor(long long F) { return (int)(F >> 40); }
+
+// Extents of a chunk's footprint.  The interpolation positions are
+// monotone in the detector column, row and slice (each ray is a line, the
+// rays of a tile are ordered), so their extremes over the tile and the
+// chunk's kTileS slices are attained at the corners; one voxel of margin on
+// each side absorbs the fixed-point rounding.  Every tap (i, i + 1) of every
+// ray of the tile then lies in [lo, lo + extent).  Host and device run this
+// same integer arithmetic.
+struct Footprint {
+    int olo, oext, zlo, zext;
+};
+
+// The tile's corner positions at the first and last slice of a chunk (4
+// along the other axis, 8 along z), advanced from chunk to chunk by exact
+// integer steps.
+struct Corners {
+    long long o[4], z[8];
+    long long dO[4], dZ[8];  // per-slice steps
+    __host__ __device__ void init(const ConeCol &ca, const ConeCol &cb, int b0, int b1, int s0) {
+        const ConeCol *cc[2] = {&ca, &cb};
+        for (int q = 0; q < 2; ++q)
+            for (int e = 0; e < 2; ++e) {
+                const long long s = s0 + (e ? kTileS - 1 : 0);
+                const ConeCol &c = *cc[q];
+                o[2 * q + e] = c.F0o + s * c.dFo;
+                dO[2 * q + e] = c.dFo;
+                for (int f = 0; f < 2; ++f) {
+                    const long long b = f ? b1 : b0;
+                    dZ[4 * q + 2 * e + f] = c.D0 + b * c.D1;
+                    z[4 * q + 2 * e + f] = c.Z0 + b * c.Z1 + s * dZ[4 * q + 2 * e + f];
+                }
+            }
+    }
+    __host__ __device__ void advance() {
+        for (int i = 0; i < 4; ++i) o[i] += kTileS * dO[i];
+        for (int i = 0; i < 8; ++i) z[i] += kTileS * dZ[i];
+    }
+    __host__ __device__ Footprint footprint() const {
+        int omin = fx40_floor(o[0]), omax = omin, zmin = fx40_floor(z[0]), zmax = zmin;
+        for (int i = 1; i < 4; ++i) {
+            const int v = fx40_floor(o[i]);
+            omin = v < omin ? v : omin;
+            omax = v > omax ? v : omax;
+        }
+        for (int i = 1; i < 8; ++i) {
+            const int v = fx40_floor(z[i]);
+            zmin = v < zmin ? v : zmin;
+            zmax = v > zmax ? v : zmax;
+        }
+        Footprint f;
+        f.olo = omin - 1;
+        f.oext = omax - omin + 4;  // taps up to omax + 1, one position of margin each side
+        f.zlo = zmin - 1;
+        f.zext = zmax - zmin + 4;
+        return f;
+    }
+};
+
+// Slices s in [0, N) where the ray's interpolation index floor(phi(s)) lies
+// in [-1, N - 1], phi(s) = F0 + s dF (a superset from float64, widened by
+// one slice; the empty set is lo > hi).
+static void valid_slices(long long F0, long long dF, int N, int *lo, int *hi) {
+    const double phi0 = (double)F0 / kFix40, sl = (double)dF / kFix40;
+    double a, b;
+    if (sl > 0) {
+        a = (-1.0 - phi0) / sl;
+        b = ((double)N - phi0) / sl;
+    } else if (sl < 0) {
+        a = ((double)N - phi0) / sl;
+        b = (-1.0 - phi0) / sl;
+    } else if (phi0 >= -1.0 && phi0 < (double)N) {
+        a = 0;
+        b = N - 1;
+    } else {
+        *lo = 1;
+        *hi = 0;
+        return;
+    }
+    const double l = std::max(0.0, floor(a) - 1.0), r = std::min((double)N - 1, ceil(b) + 1.0);
+    *lo = (int)l;
+    *hi = (int)r;
+}
+
+// Slices where the in-plane path of column record c passes within radius
+// 1 + 2h of the rotation axis: outside them both taps of the slice lie
+// outside the FOV cylinder (centres farther than 1 from the axis), where an
+// image produced on the FOV vanishes.
+static void fov_slices(const ConeCol &c, int N, int *lo, int *hi) {
+    const double h = 2.0 / N, R = 1.0 + 2.0 * h;
+    // slice coordinate -1 + (s + 1/2) h; other coordinate -1 + (phi + 1/2) h
+    const double p0 = (double)c.F0o / kFix40, sl = (double)c.dFo / kFix40;
+    const double ao = sl * h, bo = -1.0 + (p0 + 0.5) * h;  // other = ao s + bo
+    const double as = h, bs = -1.0 + 0.5 * h;              // slice = as s + bs
+    const double A = ao * ao + as * as, B = 2.0 * (ao * bo + as * bs),
+                 C = bo * bo + bs * bs - R * R;
+    const double disc = B * B - 4.0 * A * C;
+    if (disc <= 0) {
+        *lo = 1;
+        *hi = 0;
+        return;
+    }
+    const double q = sqrt(disc);
+    const double l = std::max(0.0, floor((-B - q) / (2.0 * A)) - 1.0);
+    const double r = std::min((double)N - 1, ceil((-B + q) / (2.0 * A)) + 1.0);
+    *lo = (int)l;
+    *hi = (int)r;
+}
 
 // ------------------------------------------------------------------ host
 void cone_build(inrct_geom *hd, Arena &ar) {
@@ -38,7 +161,6 @@ void cone_build(inrct_geom *hd, Arena &ar) {
     const double cv = 0.5 * (double)(g.n_v - 1);
     std::vector<ConeCol> cols((size_t)g.n_views * g.n_u);
     std::vector<ConeView> views(g.n_views);
-    bool any_x = false;
     for (int j = 0; j < g.n_views; ++j) {
         const double cs = cos(g.angles[j]), sn = sin(g.angles[j]);
         ConeView &vg = views[j];
@@ -78,19 +200,151 @@ void cone_build(inrct_geom *hd, Arena &ar) {
             c.dxy2 = (float)(dx * dx + dy * dy);
             c.dz0 = (float)dz0;
             c.hinv = (float)(h * fabs(inv));
-            if (c.ypr) vg.any_y = 1; else { vg.any_x = 1; any_x = true; }
+            if (c.ypr) vg.any_y = 1; else vg.any_x = 1;
         }
     }
+    // Projector tiles, ordered by row tile (a z band of the volume), then
+    // view, then column tile, so that the tiles running together on one XCD
+    // read one z band.  A tile whose columns mix principal axes, or whose
+    // footprint in some chunk exceeds the LDS capacity, falls back to direct
+    // gathers.
+    std::vector<ConeTile> ty, tx, tf;
+    const int nta = (int)cdiv(g.n_u, kTileA), ntb = (int)cdiv(g.n_v, kTileB);
+    for (int rt = 0; rt < ntb; ++rt)
+        for (int j = 0; j < g.n_views; ++j)
+            for (int ct = 0; ct < nta; ++ct) {
+                ConeTile t{j, ct * kTileA, rt * kTileB, 1, 0, 1, 0};
+                const int a1 = std::min(t.a0 + kTileA, g.n_u) - 1;
+                const int b1 = std::min(t.b0 + kTileB, g.n_v) - 1;
+                const ConeCol *cj = &cols[(size_t)j * g.n_u];
+                bool mixed = false;
+                int slo = N, shi = -1, flo = N, fhi = -1;
+                for (int a = t.a0; a <= a1; ++a) {
+                    const ConeCol &c = cj[a];
+                    mixed |= c.ypr != cj[t.a0].ypr;
+                    int olo, ohi;
+                    valid_slices(c.F0o, c.dFo, N, &olo, &ohi);
+                    int clo, chi;
+                    fov_slices(c, N, &clo, &chi);
+                    for (int b = t.b0; b <= b1; ++b) {
+                        int zl, zh;
+                        valid_slices(c.Z0 + (long long)b * c.Z1, c.D0 + (long long)b * c.D1, N,
+                                     &zl, &zh);
+                        const int lo = std::max(olo, zl), hi = std::min(ohi, zh);
+                        if (lo > hi) continue;
+                        slo = std::min(slo, lo);
+                        shi = std::max(shi, hi);
+                        const int fl = std::max(lo, clo), fh = std::min(hi, chi);
+                        if (fl <= fh) {
+                            flo = std::min(flo, fl);
+                            fhi = std::max(fhi, fh);
+                        }
+                    }
+                }
+                if (slo <= shi) {
+                    t.slo = slo;
+                    t.shi = shi;
+                }
+                if (flo <= fhi) {
+                    t.flo = flo;
+                    t.fhi = fhi;
+                }
+                bool fits = !mixed;
+                if (fits && t.slo <= t.shi) {
+                    Corners k;
+                    k.init(cj[t.a0], cj[a1], t.b0, b1, (t.slo / kTileS) * kTileS);
+                    for (int c0s = (t.slo / kTileS) * kTileS; fits && c0s <= t.shi;
+                         c0s += kTileS, k.advance()) {
+                        const Footprint f = k.footprint();
+                        fits = f.oext <= kFootO && f.zext <= kFootZ;
+                    }
+                }
+                (mixed || !fits ? tf : cj[t.a0].ypr ? ty : tx).push_back(t);
+            }
+    // adjoint footprints per (view, block of voxel columns)
+    const int nbk = (int)cdiv(N, kBpXY);
+    std::vector<BpCols> bpc((size_t)g.n_views * nbk * nbk);
+    for (int j = 0; j < g.n_views; ++j) {
+        const ConeView &vg = views[j];
+        const double ax = vg.Sx - vg.Cx, ay = vg.Sy - vg.Cy;
+        const double dsd = sqrt(ax * ax + ay * ay), nx = -ax / dsd, ny = -ay / dsd;
+        for (int by = 0; by < nbk; ++by)
+            for (int bx = 0; bx < nbk; ++bx) {
+                double cmin = 1e300, cmax = -1e300, kmin = 1e300, kmax = -1e300;
+                for (int q = 0; q < 4; ++q) {
+                    const double x = -1.0 + ((q & 1) ? kBpXY * bx + kBpXY + 0.5 : kBpXY * bx - 0.5) * h;
+                    const double y = -1.0 + ((q & 2) ? kBpXY * by + kBpXY + 0.5 : kBpXY * by - 0.5) * h;
+                    const double Dx = x - vg.Sx, Dy = y - vg.Sy;
+                    const double u = (ax * Dy - ay * Dx) / (vg.eux * Dy - vg.euy * Dx);
+                    const double col = u / g.du + 0.5 * (double)(g.n_u - 1);
+                    const double k = dsd / (Dx * nx + Dy * ny);
+                    cmin = std::min(cmin, col);
+                    cmax = std::max(cmax, col);
+                    kmin = std::min(kmin, k);
+                    kmax = std::max(kmax, k);
+                }
+                BpCols &e = bpc[((size_t)j * nbk + by) * nbk + bx];
+                const double lo = std::max(0.0, floor(cmin) - 1.0);
+                const double hi = std::min((double)g.n_u - 1, ceil(cmax) + 1.0);
+                e.alo = (int)lo;
+                e.na = hi >= lo ? (int)(hi - lo) + 1 : 0;
+                e.kmin = (float)(kmin * (1.0 - 1e-6));
+                e.kmax = (float)(kmax * (1.0 + 1e-6));
+            }
+    }
+    upload(ar, hd->bpcols, bpc);
+    hd->zeros.alloc(ar, 64 * sizeof(float));
+    zero_fill(ar, hd->zeros);
+    // The adjoint stages a footprint per (view, block, z band) when every
+    // one fits the caps with two rows to spare (the kernel derives the rows
+    // in single precision; its range may differ from this one by a row).
+    bool ok = true;
+    const double dvinv = 1.0 / g.dv;
+    for (size_t e = 0; ok && e < bpc.size(); ++e) {
+        ok = bpc[e].na <= kBpA;
+        for (int bz = 0; ok && bz < (int)cdiv(N, kZc); ++bz) {
+            const double z0 = (double)bz * kZc;
+            const double zlo = -1.0 + (z0 - 0.5) * h, zhi = -1.0 + (z0 + kZc + 0.5) * h;
+            const double vlo = std::min(zlo * bpc[e].kmin, zlo * bpc[e].kmax);
+            const double vhi = std::max(zhi * bpc[e].kmin, zhi * bpc[e].kmax);
+            const double blo = std::max(0.0, floor(vlo * dvinv + cv) - 2.0);
+            const double bhi = std::min((double)g.n_v - 1, ceil(vhi * dvinv + cv) + 2.0);
+            ok = bhi - blo + 1.0 <= kBpB - 2;
+        }
+    }
+    hd->bp_lds = ok;
+    // the branch-free walk: rows 1/2 to 1 voxel apart along z everywhere
+    // (E1 is linear in the slice: its end slices bound it), and the
+    // footprints fit without clamping to the detector
+    bool w2 = ok;
+    for (size_t e = 0; w2 && e < cols.size(); ++e)
+        for (int sx = 0; w2 && sx < 2; ++sx) {
+            const long long E1 = cols[e].Z1 + (long long)(sx ? N - 1 : 0) * cols[e].D1;
+            w2 = E1 >= (1LL << 39) && E1 < (1LL << 40);
+        }
+    for (size_t e = 0; w2 && e < bpc.size(); ++e)
+        for (int bz = 0; w2 && bz < (int)cdiv(N, kZc); ++bz) {
+            const double z0 = (double)bz * kZc;
+            const double zlo = -1.0 + (z0 - 0.5) * h, zhi = -1.0 + (z0 + kZc + 0.5) * h;
+            const double vlo = std::min(zlo * bpc[e].kmin, zlo * bpc[e].kmax);
+            const double vhi = std::max(zhi * bpc[e].kmin, zhi * bpc[e].kmax);
+            w2 = (ceil(vhi * dvinv + cv) + 2.0) - (floor(vlo * dvinv + cv) - 2.0) + 1.0 <= kBpB - 2;
+        }
+    hd->bp_w2 = w2;
+    std::vector<ConeTile> all;
+    all.reserve(ty.size() + tx.size() + tf.size());
+    all.insert(all.end(), ty.begin(), ty.end());
+    all.insert(all.end(), tx.begin(), tx.end());
+    all.insert(all.end(), tf.begin(), tf.end());
+    hd->n_tile_y = (int)ty.size();
+    hd->n_tile_x = (int)tx.size();
+    hd->n_tile_f = (int)tf.size();
     upload(ar, hd->ccols, cols);
     upload(ar, hd->cviews, views);
-    hd->any_x = any_x;
-    // zero-bordered copies of u in both layouts ([z][y][x] and [z][x][y]);
-    // the border is cleared once here and never written afterwards
-    const size_t Np = (size_t)N + 2 * kPad;
-    // the projector addresses the padded copy with 32-bit element offsets
-    INRCT_REQUIRE(Np * Np * Np < ((size_t)1 << 31), "cone-beam grid n = %d exceeds 1286", N);
-    hd->ut.alloc(ar, sizeof(float) * Np * Np * Np * (any_x ? 2 : 1));
-    zero_fill(ar, hd->ut);
+    upload(ar, hd->tiles, all);
+    // the projector addresses the grid with 32-bit element offsets
+    INRCT_REQUIRE((size_t)N * N * N < ((size_t)1 << 31), "cone-beam grid n = %d exceeds 1290",
+                  N);
 }
 
 // ---------------------------------------------------------------- device
@@ -161,100 +415,199 @@ __device__ __forceinline__ void range40_exact(long long F0, long long dF, int N,
     *hi = r;
 }
 
-// up[z+kPad][y+kPad][x+kPad] = u[z][y][x] and (if ut) ut[z+kPad][x+kPad][y+kPad] = u[z][y][x]
-__global__ __launch_bounds__(256) void k_pad_copy(const float *__restrict__ u,
-                                                  float *__restrict__ up,
-                                                  float *__restrict__ ut, int N) {
-    __shared__ float tile[32][33];
-    const int Np = N + 2 * kPad;
-    const int z = blockIdx.z;
-    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
-    const size_t base = (size_t)z * N * N;
-    const size_t pbase = (size_t)(z + kPad) * Np * Np;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int k = ty; k < 32; k += 8) {
-        const int y = y0 + k, x = x0 + tx;
-        if (x < N && y < N) {
-            const float val = u[base + (size_t)y * N + x];
-            tile[k][tx] = val;
-            up[pbase + (size_t)(y + kPad) * Np + x + kPad] = val;
+// --------------------------------------------------------------------- P
+// z = P u, a tile of kTileA columns x kTileB rows of one view per
+// workgroup: lane = column, wave w = rows kRows w .. kRows (w + 1) - 1 of the
+// tile, so each thread integrates kRows rays of one column (they share the
+// in-plane position and its weight).  Slices are visited in chunks of kTileS: the
+// chunk's footprint of u (every tap of every ray of the tile, zero outside
+// the grid) is staged in LDS with coalesced loads, then every sample reads
+// its four taps from LDS.  Two workgroups share a CU, so one stages while
+// the other integrates.
+// Stages the footprint with direct global -> LDS copies (each lane's dword
+// lands at the wave's uniform LDS address + 4 lane); lanes whose tap lies
+// outside the grid copy a zero.  Consecutive lanes copy consecutive LDS
+// dwords: a run of o for y-principal rays, (z, s) pairs for x-principal
+// ones.  The copies are waited for at the next barrier.
+template <bool YPR>
+__device__ __forceinline__ void stage_footprint(float *__restrict__ L, const float *__restrict__ u,
+                                                const float *__restrict__ zeros, int N, int s0,
+                                                const Footprint &f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long NN = (long long)N * N;
+    const bool inside = f.olo >= 0 && f.olo + f.oext <= N && f.zlo >= 0 && f.zlo + f.zext <= N &&
+                        s0 + kTileS <= N;
+    if (YPR) {
+        // rows (s, z): lane = o; a second pass covers o >= 64, its lanes
+        // past the footprint copying nothing (a row holds kLdsZY floats)
+        for (int ob = 0; ob < f.oext; ob += 64) {
+            if (ob > 0 && ob + lane >= f.oext) break;
+            if (inside) {
+                // every tap inside the grid: uniform row pointers
+                for (int sl = 0; sl < kTileS; ++sl) {
+                    const float *row = u + (((long long)(f.zlo + w) * N + s0 + sl) * N + f.olo + ob);
+                    for (int z = w; z < f.zext; z += 4, row += 4 * NN)
+                        __builtin_amdgcn_global_load_lds(row + lane, L + sl * kLdsSY + z * kLdsZY + ob,
+                                                         4, 0, 0);
+                }
+                continue;
+            }
+            const int o = f.olo + ob + lane;
+            const bool o_in = o >= 0 && o < N;
+            for (int sl = 0; sl < kTileS; ++sl) {
+                const int sg = s0 + sl;
+                const bool so = o_in && sg < N;
+                for (int z = w; z < f.zext; z += 4) {
+                    const int zg = f.zlo + z;
+                    const float *src =
+                        so && zg >= 0 && zg < N ? u + (zg * NN + (long long)sg * N + o) : zeros + lane;
+                    __builtin_amdgcn_global_load_lds(src, L + sl * kLdsSY + z * kLdsZY + ob, 4, 0, 0);
+                }
+            }
         }
-    }
-    if (ut == nullptr) return;
-    __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-        const int x = x0 + k, y = y0 + tx;
-        if (x < N && y < N) ut[pbase + (size_t)(x + kPad) * Np + y + kPad] = tile[tx][k];
+    } else {
+        // rows (o, z): lane = (z offset, s), eight z rows of eight slices
+        const int sl = lane & 7, zq = lane >> 3;
+        if (inside) {
+            const long long loff = zq * NN + sl;
+            for (int zb = 0; zb < f.zext; zb += 8) {
+                if (zb + zq >= f.zext) break;  // (this lane's z rows are done)
+                const float *row = u + (((long long)(f.zlo + zb) * N + f.olo + w) * N + s0) + loff;
+                for (int o = w; o < f.oext; o += 4, row += 4 * N)
+                    __builtin_amdgcn_global_load_lds(row, L + o * kLdsOX + zb * kLdsZX, 4, 0, 0);
+            }
+            return;
+        }
+        const int sg = s0 + sl;
+        for (int o = w; o < f.oext; o += 4) {
+            const int og = f.olo + o;
+            const bool oin = og >= 0 && og < N && sg < N;
+            for (int zb = 0; zb < f.zext; zb += 8) {
+                const int zg = f.zlo + zb + zq;
+                const float *src = oin && zb + zq < f.zext && zg >= 0 && zg < N
+                                       ? u + (zg * NN + (long long)og * N + sg)
+                                       : zeros + lane;
+                __builtin_amdgcn_global_load_lds(src, L + o * kLdsOX + zb * kLdsZX, 4, 0, 0);
+            }
+        }
     }
 }
 
-// One ray per lane.  Reads the zero-bordered copies: over the exact slice
-// range every tap index lies in [-1, N], inside the kPad-wide zero border,
-// so no tap needs a bounds test.
-__global__ __launch_bounds__(256) void k_cone_fwd(ConeDev g, const float *__restrict__ up,
-                                                  const float *__restrict__ utp,
-                                                  float *__restrict__ z, int ncx, int ncy) {
+constexpr int kRows = kTileB / 4;  // rays per thread (one column)
+
+template <bool YPR>
+__global__ __launch_bounds__(256, 2) void k_cone_fwd_lds(ConeDev g, const ConeTile *__restrict__ tiles,
+                                                         int ntiles, const float *__restrict__ u,
+                                                         float *__restrict__ zout, int fov_only) {
+    __shared__ float L[YPR ? kLdsFloatsY : kLdsFloatsX];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    if (lb < 0) return;
-    // a wave is an 8 x 8 patch of rays (columns x rows); a block 16 x 16.
-    // Blocks go in pairs of row tiles, column tiles next, then row-tile
-    // pairs, then views: both tiles that share a boundary row of voxels,
-    // and the tiles beside them, run at about the same time.
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ngr = (ncy + 1) >> 1;
-    const int rt = ((lb / (2 * ncx)) % ngr) * 2 + (lb & 1);
-    const int a = ((lb >> 1) % ncx) * 16 + (wave & 1) * 8 + (lane & 7);
-    const int b = rt * 16 + (wave >> 1) * 8 + (lane >> 3);
-    const int j = lb / (2 * ncx * ngr);
-    if (a >= g.Nu || b >= g.Nv) return;
-    const ConeCol c = g.col[(size_t)j * g.Nu + a];
-    const long long F0z = c.Z0 + (long long)b * c.Z1;
-    const long long dFz = c.D0 + (long long)b * c.D1;
+    if (lb < 0 || lb >= ntiles) return;
+    const ConeTile t = tiles[lb];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a1 = min(t.a0 + kTileA, g.Nu) - 1, b1 = min(t.b0 + kTileB, g.Nv) - 1;
+    // lanes past the detector edge follow the last column / row (their
+    // positions stay inside the footprint); their results are not written
+    const int a = min(t.a0 + lane, a1);
+    const ConeCol *cj = g.col + (size_t)t.j * g.Nu;
+    const ConeCol c = cj[a];
+    const ConeCol ca = cj[t.a0], cb = cj[a1];
+    int brow[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) brow[r] = min(t.b0 + kRows * w + r, b1);
+    float acc[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
+    const int lo = fov_only ? t.flo : t.slo, hi = fov_only ? t.fhi : t.shi;
     const int N = g.N;
-    const int Np = N + 2 * kPad, Np2 = Np * Np;
-    int lo1, hi1, lo2, hi2;
-    range40_exact(c.F0o, c.dFo, N, &lo1, &hi1);
-    range40_exact(F0z, dFz, N, &lo2, &hi2);
-    const int lo = max(lo1, lo2), hi = min(hi1, hi2);
-    const float *__restrict__ src = c.ypr ? up : utp;
-    long long Fo = c.F0o + (long long)lo * c.dFo;
-    long long Fz = F0z + (long long)lo * dFz;
-    // element offset of tap (iz, s, io): (iz + kPad) Np2 + (s + kPad) Np + io + kPad
-    int srow = (lo + kPad) * Np + kPad * Np2 + kPad;
-    float acc = 0.f;
-    // Four steps per iteration, all taps loaded before any is used, so each
-    // wave keeps sixteen gathers in flight; the sum stays in step order.
-    int s = lo;
-    for (; s + 3 <= hi; s += 4) {
-        float v[4][4], wo[4], wz[4];
+    const int sfirst = (lo / kTileS) * kTileS;
+    // ray positions at the chunk's first slice, relative to the footprint's
+    // corner (olo, zlo); corners of the tile for the footprint
+    Corners k;
+    k.init(ca, cb, t.b0, b1, sfirst);
+    long long Fo = c.F0o + (long long)sfirst * c.dFo, Fz[kRows], dFz[kRows];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const long long Foq = Fo + q * c.dFo, Fzq = Fz + q * dFz;
-            const int e = srow + q * Np + fx40_int(Fzq) * Np2 + fx40_int(Foq);
-            wo[q] = fx40_frac(Foq);
-            wz[q] = fx40_frac(Fzq);
-            v[q][0] = src[e];
-            v[q][1] = src[e + 1];
-            v[q][2] = src[e + Np2];
-            v[q][3] = src[e + Np2 + 1];
+    for (int r = 0; r < kRows; ++r) {
+        const long long b = brow[r];
+        dFz[r] = c.D0 + b * c.D1;
+        Fz[r] = c.Z0 + b * c.Z1 + (long long)sfirst * dFz[r];
+    }
+    int olo = 0, zlo = 0;
+    for (int s0 = sfirst; lo <= hi && s0 <= hi; s0 += kTileS, k.advance()) {
+        const Footprint f = k.footprint();
+        __syncthreads();  // the previous chunk's reads are done
+        stage_footprint<YPR>(L, u, g.zeros, N, s0, f);
+        // re-base the positions on this chunk's corner
+        Fo += (long long)(olo - f.olo) * (1LL << 40);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) Fz[r] += (long long)(zlo - f.zlo) * (1LL << 40);
+        olo = f.olo;
+        zlo = f.zlo;
+        __syncthreads();
+#pragma unroll
+        for (int sl = 0; sl < kTileS; ++sl) {
+            const int io = fx40_int(Fo);
+            const float fo = fx40_frac(Fo);
+            const float *Ls = L + (YPR ? sl * kLdsSY + io : sl + io * kLdsOX);
+            constexpr int co = YPR ? 1 : kLdsOX, cz = YPR ? kLdsZY : kLdsZX;
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                const int iz = fx40_int(Fz[r]);
+                const float fz = fx40_frac(Fz[r]);
+                const float *p = Ls + iz * cz;
+                const float v00 = p[0], v01 = p[co], v10 = p[cz], v11 = p[cz + co];
+                const float t0 = fmaf(fo, v01 - v00, v00);
+                const float t1 = fmaf(fo, v11 - v10, v10);
+                acc[r] += fmaf(fz, t1 - t0, t0);
+                Fz[r] += dFz[r];
+            }
+            Fo += c.dFo;
         }
+    }
+    if (t.a0 + lane > a1) return;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            acc += (1.f - wz[q]) * ((1.f - wo[q]) * v[q][0] + wo[q] * v[q][1]) +
-                   wz[q] * ((1.f - wo[q]) * v[q][2] + wo[q] * v[q][3]);
-        Fo += 4 * c.dFo;
-        Fz += 4 * dFz;
-        srow += 4 * Np;
+    for (int r = 0; r < kRows; ++r) {
+        const int b = t.b0 + kRows * w + r;
+        if (b <= b1) zout[((size_t)t.j * g.Nv + b) * g.Nu + a] = acc[r] * cone_step(g, c, b);
     }
-    for (; s <= hi; ++s, Fo += c.dFo, Fz += dFz, srow += Np) {
-        const int io = fx40_int(Fo), iz = fx40_int(Fz);
-        const float wo = fx40_frac(Fo), wz = fx40_frac(Fz);
-        const int e = srow + iz * Np2 + io;
-        const float v00 = src[e], v01 = src[e + 1];
-        const float v10 = src[e + Np2], v11 = src[e + Np2 + 1];
-        acc += (1.f - wz) * ((1.f - wo) * v00 + wo * v01) + wz * ((1.f - wo) * v10 + wo * v11);
+}
+
+// The same tile by direct gathers from u with bounds tests, for tiles whose
+// columns mix principal axes or whose footprint exceeds the LDS capacity.
+__global__ __launch_bounds__(256) void k_cone_fwd_direct(ConeDev g,
+                                                         const ConeTile *__restrict__ tiles,
+                                                         int ntiles, const float *__restrict__ u,
+                                                         float *__restrict__ zout) {
+    if ((int)blockIdx.x >= ntiles) return;
+    const ConeTile t = tiles[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = t.a0 + lane;
+    if (a >= g.Nu) return;
+    const ConeCol c = g.col[(size_t)t.j * g.Nu + a];
+    const int N = g.N;
+    const long long NN = (long long)N * N;
+    auto at = [&](int iz, int is, int io) -> float {
+        if (iz < 0 || iz >= N || io < 0 || io >= N) return 0.f;
+        return c.ypr ? u[iz * NN + (long long)is * N + io] : u[iz * NN + (long long)io * N + is];
+    };
+    for (int r = 0; r < kRows; ++r) {
+        const int b = t.b0 + kRows * w + r;
+        if (b >= g.Nv) break;
+        const long long F0z = c.Z0 + (long long)b * c.Z1, dFz = c.D0 + (long long)b * c.D1;
+        int lo1, hi1, lo2, hi2;
+        range40_exact(c.F0o, c.dFo, N, &lo1, &hi1);
+        range40_exact(F0z, dFz, N, &lo2, &hi2);
+        float acc = 0.f;
+        for (int s = max(lo1, lo2); s <= min(hi1, hi2); ++s) {
+            const long long Fo = c.F0o + (long long)s * c.dFo, Fz = F0z + (long long)s * dFz;
+            const int io = fx40_int(Fo), iz = fx40_int(Fz);
+            const float fo = fx40_frac(Fo), fz = fx40_frac(Fz);
+            const float t0 = fmaf(fo, at(iz, s, io + 1) - at(iz, s, io), at(iz, s, io));
+            const float t1 =
+                fmaf(fo, at(iz + 1, s, io + 1) - at(iz + 1, s, io), at(iz + 1, s, io));
+            acc += fmaf(fz, t1 - t0, t0);
+        }
+        zout[((size_t)t.j * g.Nv + b) * g.Nu + a] = acc * cone_step(g, c, b);
     }
-    z[((size_t)j * g.Nv + b) * g.Nu + a] = acc * cone_step(g, c, b);
 }
 
 // rs = r * step length (applied on the ray side of P^T)
@@ -292,88 +645,291 @@ __device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, 
     *hi = (int)r;
 }
 
-// (P^T r) for voxels (ix, iy, z0 .. z0 + ZC - 1), accumulated into acc.
-// rs is the step-weighted residual.
+// (P^T r) of view j for voxels (ix, iy, z0 .. z0 + ZC - 1), accumulated
+// into acc.  The step-weighted residual of the view is read as R[(b - blo)
+// rstride + (a - alo)] for detector rows [blo, bhi] and columns [alo, ahi],
+// and column a's record as C[a - alo]; both may be staged copies in LDS or
+// the arrays themselves.  Every voxel receives its terms in increasing row
+// order, whatever the source.
 template <int ZC>
-__device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__restrict__ rs,
-                                            int ix, int iy, int z0, float (&acc)[ZC]) {
+__device__ __forceinline__ void cone_gather_view(const ConeDev &g, const ConeView &vg,
+                                                 const float *__restrict__ R, int rstride,
+                                                 const ConeCol *__restrict__ C, int alo, int ahi,
+                                                 int blo, int bhi, int ix, int iy, int z0,
+                                                 float (&acc)[ZC]) {
     const float h = (float)g.h;
     const float x = (float)(-1.0 + (ix + 0.5) * g.h), y = (float)(-1.0 + (iy + 0.5) * g.h);
-    const int Nu = g.Nu, Nv = g.Nv;
-    for (int j = 0; j < g.V; ++j) {
-        const ConeView vg = g.view[j];
-        const float *rj = rs + (size_t)j * Nv * Nu;
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool ypass = pass == 0;
-            if (ypass ? !vg.any_y : !vg.any_x) continue;
-            const int s = ypass ? iy : ix, o = ypass ? ix : iy;
-            int lo, hi;
-            if (ypass) cone_cols(g, vg, x - h, y, x + h, y, &lo, &hi);
-            else cone_cols(g, vg, x, y - h, x, y + h, &lo, &hi);
-            for (int a = lo; a <= hi; ++a) {
-                const ConeCol c = g.col[(size_t)j * Nu + a];
-                if ((c.ypr != 0) != ypass) continue;
-                const long long Fo = c.F0o + (long long)s * c.dFo;
-                const int io = fx40_int(Fo);
-                if (io != o && io != o - 1) continue;
-                const float fo = fx40_frac(Fo);
-                const float wo = io == o ? 1.f - fo : fo;
-                const long long E0 = c.Z0 + (long long)s * c.D0;
-                const long long E1 = c.Z1 + (long long)s * c.D1;  // > 0
-                // first row whose stencil reaches z0 - 1
-                const long long lo_t = (long long)(z0 - 1) << 40;
-                // row estimate in single precision; the walks below make it exact
-                float bd = floorf((float)(lo_t - E0) * __builtin_amdgcn_rcpf((float)E1)) - 1.f;
-                bd = bd < 0.f ? 0.f : (bd > (float)Nv ? (float)Nv : bd);
-                int b = (int)bd;
-                long long ph = E0 + (long long)b * E1;
-                while (b > 0 && ph - E1 >= lo_t) {
-                    --b;
-                    ph -= E1;
-                }
-                while (b < Nv && ph < lo_t) {
-                    ++b;
-                    ph += E1;
-                }
-                // One pass over the rows from b on: a row whose stencil
-                // starts at voxel i0 gives (1 - w) to i0 and w to i0 + 1.
-                // Every voxel still receives its terms in increasing row
-                // order with the same products, so the sums are unchanged.
-                const float *rp = rj + a + (size_t)b * Nu;
-                while (b < Nv && fx40_int(ph) == z0 - 1) {
-                    acc[0] += wo * fx40_frac(ph) * rp[0];
-                    ++b;
-                    ph += E1;
-                    rp += Nu;
-                }
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool ypass = pass == 0;
+        if (ypass ? !vg.any_y : !vg.any_x) continue;
+        const int s = ypass ? iy : ix, o = ypass ? ix : iy;
+        int lo, hi;
+        if (ypass) cone_cols(g, vg, x - h, y, x + h, y, &lo, &hi);
+        else cone_cols(g, vg, x, y - h, x, y + h, &lo, &hi);
+        lo = max(lo, alo);
+        hi = min(hi, ahi);
+        for (int a = lo; a <= hi; ++a) {
+            const ConeCol c = C[a - alo];
+            if ((c.ypr != 0) != ypass) continue;
+            const long long Fo = c.F0o + (long long)s * c.dFo;
+            const int io = fx40_int(Fo);
+            if (io != o && io != o - 1) continue;
+            const float fo = fx40_frac(Fo);
+            const float wo = io == o ? 1.f - fo : fo;
+            const long long E0 = c.Z0 + (long long)s * c.D0;
+            const long long E1 = c.Z1 + (long long)s * c.D1;  // > 0
+            // first row whose stencil reaches z0 - 1
+            const long long lo_t = (long long)(z0 - 1) * (1LL << 40);
+            // row estimate in single precision; the walks below make it exact
+            float bd = floorf((float)(lo_t - E0) * __builtin_amdgcn_rcpf((float)E1)) - 1.f;
+            bd = bd < (float)blo ? (float)blo : (bd > (float)(bhi + 1) ? (float)(bhi + 1) : bd);
+            int b = (int)bd;
+            long long ph = E0 + (long long)b * E1;
+            while (b > blo && ph - E1 >= lo_t) {
+                --b;
+                ph -= E1;
+            }
+            while (b <= bhi && ph < lo_t) {
+                ++b;
+                ph += E1;
+            }
+            // One pass over the rows from b on: a row whose stencil starts
+            // at voxel i0 gives (1 - w) to i0 and w to i0 + 1.
+            int ri = (b - blo) * rstride + (a - alo);
+            while (b <= bhi && fx40_int(ph) == z0 - 1) {
+                acc[0] += wo * fx40_frac(ph) * R[ri];
+                ++b;
+                ph += E1;
+                ri += rstride;
+            }
 #pragma unroll
-                for (int jz = 0; jz < ZC; ++jz) {
-                    while (b < Nv && fx40_int(ph) == z0 + jz) {
-                        const float w = fx40_frac(ph);
-                        const float r = rp[0];
-                        acc[jz] += wo * (1.f - w) * r;
-                        if (jz + 1 < ZC) acc[jz + 1] += wo * w * r;
-                        ++b;
-                        ph += E1;
-                        rp += Nu;
-                    }
+            for (int jz = 0; jz < ZC; ++jz) {
+                while (b <= bhi && fx40_int(ph) == z0 + jz) {
+                    const float w = fx40_frac(ph);
+                    const float r = R[ri];
+                    acc[jz] += wo * (1.f - w) * r;
+                    if (jz + 1 < ZC) acc[jz + 1] += wo * w * r;
+                    ++b;
+                    ph += E1;
+                    ri += rstride;
                 }
             }
         }
     }
 }
 
-constexpr int kZc = 16;
+// cone_gather_view for geometries whose detector rows are between half a
+// voxel and one voxel apart along z at every column and slice (E1 in
+// [1/2, 1)): every voxel band [z, z + 1) then holds one or two rows, so the
+// walk visits, for each band, the band's first row and the row after it
+// (used only when it lies in the band), with no data-dependent branch.  R
+// must hold every row whose stencil reaches the segment, zeros for rows off
+// the detector, and one more row (the walk reads a row past the last).
+template <int ZC>
+__device__ __forceinline__ void cone_gather_view_w2(const ConeDev &g, const ConeView &vg,
+                                                    const float *__restrict__ R, int rstride,
+                                                    const ConeCol *__restrict__ C, int alo, int ahi,
+                                                    int blo, int ix, int iy, int z0,
+                                                    float (&acc)[ZC]) {
+    const float h = (float)g.h;
+    const float x = (float)(-1.0 + (ix + 0.5) * g.h), y = (float)(-1.0 + (iy + 0.5) * g.h);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool ypass = pass == 0;
+        if (ypass ? !vg.any_y : !vg.any_x) continue;
+        const int s = ypass ? iy : ix, o = ypass ? ix : iy;
+        int lo, hi;
+        if (ypass) cone_cols(g, vg, x - h, y, x + h, y, &lo, &hi);
+        else cone_cols(g, vg, x, y - h, x, y + h, &lo, &hi);
+        lo = max(lo, alo);
+        hi = min(hi, ahi);
+        for (int a = lo; a <= hi; ++a) {
+            const ConeCol c = C[a - alo];
+            if ((c.ypr != 0) != ypass) continue;
+            const long long Fo = c.F0o + (long long)s * c.dFo;
+            const int io = fx40_int(Fo);
+            if (io != o && io != o - 1) continue;
+            const float fo = fx40_frac(Fo);
+            const float wo = io == o ? 1.f - fo : fo;
+            const long long E0 = c.Z0 + (long long)s * c.D0;
+            const long long E1 = c.Z1 + (long long)s * c.D1;
+            // the first row whose stencil reaches z0 - 1: estimate, then exact
+            const long long lo_t = (long long)(z0 - 1) * (1LL << 40);
+            int b = (int)floorf((float)(lo_t - E0) * __builtin_amdgcn_rcpf((float)E1));
+            long long ph = E0 + (long long)b * E1;
+            if (ph >= lo_t) {
+                --b;
+                ph -= E1;
+            }
+            if (ph < lo_t) {
+                ++b;
+                ph += E1;
+            }
+            if (ph < lo_t) {
+                ++b;
+                ph += E1;
+            }
+            int ri = (b - blo) * rstride + (a - alo);
+            // band jz = -1 .. ZC - 1: rows with floor(phi) = z0 + jz give
+            // (1 - w) to voxel jz and w to voxel jz + 1
+#pragma unroll
+            for (int jz = -1; jz < ZC; ++jz) {
+                const float wA = fx40_frac(ph);
+                const float tA = wo * R[ri];
+                const long long phB = ph + E1;
+                const bool inB = fx40_int(phB) == z0 + jz;
+                const float wB = fx40_frac(phB);
+                const float tB = inB ? wo * R[ri + rstride] : 0.f;
+                const float pA = tA * wA, pB = tB * wB;
+                if (jz >= 0) acc[jz] += (tA - pA) + (tB - pB);
+                if (jz + 1 < ZC) acc[jz + 1] += pA + pB;
+                ph = inB ? phB + E1 : phB;
+                ri += inB ? 2 * rstride : rstride;
+            }
+        }
+    }
+}
 
-__global__ __launch_bounds__(256) void k_cone_bp(ConeDev g, const float *__restrict__ rs,
-                                                 float *__restrict__ v, int nbx, int nby) {
+// (P^T r) for voxels (ix, iy, z0 .. z0 + ZC - 1) over all views, reading the
+// residual and the column records in place.
+template <int ZC>
+__device__ __forceinline__ void cone_gather(const ConeDev &g, const float *__restrict__ rs,
+                                            int ix, int iy, int z0, float (&acc)[ZC]) {
+    for (int j = 0; j < g.V; ++j)
+        cone_gather_view<ZC>(g, g.view[j], rs + (size_t)j * g.Nv * g.Nu, g.Nu,
+                             g.col + (size_t)j * g.Nu, 0, g.Nu - 1, 0, g.Nv - 1, ix, iy, z0, acc);
+}
+
+
+struct BpFoot {
+    int alo, na, blo, nb;
+};
+
+// Detector footprint of view j for the block (bx, by) and the z band
+// [z0, z0 + kZc): the block's columns, and the rows whose stencil reaches
+// z in [z0 - 1, z0 + kZc] (world z from the band, times D_sd / d), with two
+// rows of margin.
+template <bool W2>
+__device__ __forceinline__ BpFoot bp_foot(const ConeDev &g, int j, int nbk, int bx, int by,
+                                          int z0) {
+    const BpCols e = g.bpc[((size_t)j * nbk + by) * nbk + bx];
+    const float h = (float)g.h;
+    const float zlo = -1.f + ((float)z0 - 0.5f) * h, zhi = -1.f + ((float)z0 + kZc + 0.5f) * h;
+    const float vlo = fminf(zlo * e.kmin, zlo * e.kmax), vhi = fmaxf(zhi * e.kmin, zhi * e.kmax);
+    const float inv = 1.f / g.dvf;
+    // the branch-free walk reads rows off the detector too (staged as zeros)
+    int blo = (int)floorf(vlo * inv + g.cvf) - 2, bhi = (int)ceilf(vhi * inv + g.cvf) + 2;
+    if (!W2) {
+        blo = max(0, blo);
+        bhi = min(g.Nv - 1, bhi);
+    }
+    BpFoot f;
+    f.alo = e.alo;
+    f.na = min(e.na, kBpA);
+    f.blo = blo;
+    // (the host checked that every footprint fits with two rows to spare;
+    // the clamp only guards the staging buffer)
+    f.nb = min(bhi >= blo ? bhi - blo + 1 : 0, kBpB);
+    return f;
+}
+
+// v = P^T r on the full grid.  A block is 16 x 16 voxel columns (a wave an
+// 8 x 8 patch) by kZc voxels along z, one thread per column segment.  View
+// by view, the block's detector footprint of the step-weighted residual and
+// the footprint's column records are staged in LDS (the next view's values
+// are loaded into registers while the current view is gathered), so the
+// row walks read LDS.  Used when every footprint fits the caps (checked when
+// the geometry is built).  Gather only: no atomics.
+template <bool W2>
+__global__ __launch_bounds__(256) void k_cone_bp_lds(ConeDev g, const float *__restrict__ rs,
+                                                     float *__restrict__ v, int nbk) {
+    __shared__ float R[2][(kBpB + 1) * kBpRs];
+    __shared__ ConeCol C[2][kBpA];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb < 0) return;
-    // a wave is an 8 x 8 patch of (x, y) voxel columns; a block 16 x 16
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ix = (lb % nbx) * 16 + (wave & 1) * 8 + (lane & 7);
-    const int iy = ((lb / nbx) % nby) * 16 + (wave >> 1) * 8 + (lane >> 3);
-    const int z0 = (lb / (nbx * nby)) * kZc;
+    const int bx = lb % nbk, by = (lb / nbk) % nbk, bz = lb / (nbk * nbk);
+    const int ix = bx * kBpXY + (wave & 1) * 8 + (lane & 7);
+    const int iy = by * kBpXY + (wave >> 1) * 8 + (lane >> 3);
+    const int z0 = bz * kZc;
+    const bool active = ix < g.N && iy < g.N;
+    float acc[kZc];
+#pragma unroll
+    for (int i = 0; i < kZc; ++i) acc[i] = 0.f;
+    // staging: thread t holds detector column alo + (t & 63) of rows
+    // blo + (t >> 6) + 4 q, and dwords (t & 15) + 16 q' of the records
+    constexpr int kRq = kBpB / 4, kCw = (int)(sizeof(ConeCol) / 4);
+    constexpr int kCq = kBpA * kCw / 256;
+    float rv[kRq];
+    int cv[kCq];
+    auto load = [&](int j, const BpFoot &f) {
+        const float *rj = rs + (size_t)j * g.Nv * g.Nu;
+        const int col = threadIdx.x & 63;
+#pragma unroll
+        for (int q = 0; q < kRq; ++q) {
+            const int row = (threadIdx.x >> 6) + 4 * q;
+            const int b = f.blo + row;
+            rv[q] = col < f.na && row < f.nb && b >= 0 && b < g.Nv
+                        ? rj[(size_t)b * g.Nu + f.alo + col]
+                        : 0.f;
+        }
+        const int *cj = (const int *)(g.col + (size_t)j * g.Nu + f.alo);
+#pragma unroll
+        for (int q = 0; q < kCq; ++q) {
+            const int w = threadIdx.x + 256 * q;
+            cv[q] = w < f.na * kCw ? cj[w] : 0;
+        }
+    };
+    auto store = [&](int buf, const BpFoot &f) {
+        const int col = threadIdx.x & 63;
+#pragma unroll
+        for (int q = 0; q < kRq; ++q) R[buf][((threadIdx.x >> 6) + 4 * q) * kBpRs + col] = rv[q];
+        int *cw = (int *)C[buf];
+#pragma unroll
+        for (int q = 0; q < kCq; ++q) cw[threadIdx.x + 256 * q] = cv[q];
+    };
+    BpFoot f = bp_foot<W2>(g, 0, nbk, bx, by, z0);
+    load(0, f);
+    store(0, f);
+    __syncthreads();
+    for (int j = 0; j < g.V; ++j) {
+        const int buf = j & 1;
+        BpFoot fn;
+        if (j + 1 < g.V) {
+            fn = bp_foot<W2>(g, j + 1, nbk, bx, by, z0);
+            load(j + 1, fn);
+        }
+        if (active && f.na > 0 && f.nb > 0) {
+            if (W2)
+                cone_gather_view_w2<kZc>(g, g.view[j], R[buf], kBpRs, C[buf], f.alo,
+                                         f.alo + f.na - 1, f.blo, ix, iy, z0, acc);
+            else
+                cone_gather_view<kZc>(g, g.view[j], R[buf], kBpRs, C[buf], f.alo, f.alo + f.na - 1,
+                                      f.blo, f.blo + f.nb - 1, ix, iy, z0, acc);
+        }
+        if (j + 1 < g.V) {
+            store(buf ^ 1, fn);
+            f = fn;
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    const size_t NN = (size_t)g.N * g.N;
+#pragma unroll
+    for (int i = 0; i < kZc; ++i)
+        if (z0 + i < g.N) v[(size_t)(z0 + i) * NN + (size_t)iy * g.N + ix] = acc[i];
+}
+
+// v = P^T r reading the residual in place, for geometries whose footprints
+// exceed the LDS caps.
+__global__ __launch_bounds__(256) void k_cone_bp_direct(ConeDev g, const float *__restrict__ rs,
+                                                        float *__restrict__ v, int nbk) {
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb < 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int bx = lb % nbk, by = (lb / nbk) % nbk, bz = lb / (nbk * nbk);
+    const int ix = bx * kBpXY + (wave & 1) * 8 + (lane & 7);
+    const int iy = by * kBpXY + (wave >> 1) * 8 + (lane >> 3);
+    const int z0 = bz * kZc;
     if (ix >= g.N || iy >= g.N) return;
     float acc[kZc];
 #pragma unroll
@@ -398,24 +954,24 @@ __global__ __launch_bounds__(256) void k_cone_bp_at(ConeDev g, const float *__re
 }
 
 // ----------------------------------------------------------- host wrappers
-void cone_project(inrct_geom *hd, const float *u, float *z, hipStream_t s) {
+void cone_project(inrct_geom *hd, const float *u, float *z, bool fov_only, hipStream_t s) {
     const ConeDev d = hd->cone();
-    const size_t Np = (size_t)d.N + 2 * kPad;
-    float *up = hd->ut.as<float>();
-    float *utp = hd->any_x ? up + Np * Np * Np : up;
-    hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)cdiv(d.N, 32), (unsigned)cdiv(d.N, 32), d.N),
-                       dim3(256), 0, s, u, up, hd->any_x ? utp : nullptr, d.N);
-    INRCT_CHECK_LAUNCH();
-    const int ncx = (int)cdiv(d.Nu, 16), ncy = (int)cdiv(d.Nv, 16);
-    const int ngr = (ncy + 1) / 2;  // row-tile pairs (the last may be half empty)
-    // The launch reserves 54 KB of LDS it does not use, so that at most two
-    // blocks share a CU: with fewer rays in flight per XCD, the voxel lines a
-    // block fetches are still in L2 when the neighbouring blocks read them
-    // (10.3 -> 8.6 ms at 501^3; four blocks per CU 9.7 ms, three 9.3 ms, one
-    // 12.5 ms).
-    hipLaunchKernelGGL(k_cone_fwd, dim3((unsigned)(ncx * ngr * 2 * d.V)), dim3(256),
-                       kConeFwdLdsCap, s, d, up, utp, z, ncx, ncy);
-    INRCT_CHECK_LAUNCH();
+    const ConeTile *t = hd->tiles.as<ConeTile>();
+    if (hd->n_tile_y > 0) {
+        hipLaunchKernelGGL(k_cone_fwd_lds<true>, dim3((unsigned)hd->n_tile_y), dim3(256), 0, s, d,
+                           t, hd->n_tile_y, u, z, fov_only ? 1 : 0);
+        INRCT_CHECK_LAUNCH();
+    }
+    if (hd->n_tile_x > 0) {
+        hipLaunchKernelGGL(k_cone_fwd_lds<false>, dim3((unsigned)hd->n_tile_x), dim3(256), 0, s,
+                           d, t + hd->n_tile_y, hd->n_tile_x, u, z, fov_only ? 1 : 0);
+        INRCT_CHECK_LAUNCH();
+    }
+    if (hd->n_tile_f > 0) {
+        hipLaunchKernelGGL(k_cone_fwd_direct, dim3((unsigned)hd->n_tile_f), dim3(256), 0, s, d,
+                           t + hd->n_tile_y + hd->n_tile_x, hd->n_tile_f, u, z);
+        INRCT_CHECK_LAUNCH();
+    }
 }
 
 static const float *cone_prescale(inrct_geom *hd, const float *r, hipStream_t s) {
@@ -430,9 +986,16 @@ static const float *cone_prescale(inrct_geom *hd, const float *r, hipStream_t s)
 void cone_backproject(inrct_geom *hd, const float *r, float *v, hipStream_t s) {
     const float *rs = cone_prescale(hd, r, s);
     const ConeDev d = hd->cone();
-    const int nbx = (int)cdiv(d.N, 16), nby = (int)cdiv(d.N, 16), nbz = (int)cdiv(d.N, kZc);
-    hipLaunchKernelGGL(k_cone_bp, dim3((unsigned)(nbx * nby * nbz)), dim3(256), 0, s, d, rs, v,
-                       nbx, nby);
+    const int nbk = (int)cdiv(d.N, kBpXY), nbz = (int)cdiv(d.N, kZc);
+    if (hd->bp_lds && hd->bp_w2)
+        hipLaunchKernelGGL(k_cone_bp_lds<true>, dim3((unsigned)(nbk * nbk * nbz)), dim3(256), 0, s,
+                           d, rs, v, nbk);
+    else if (hd->bp_lds)
+        hipLaunchKernelGGL(k_cone_bp_lds<false>, dim3((unsigned)(nbk * nbk * nbz)), dim3(256), 0, s,
+                           d, rs, v, nbk);
+    else
+        hipLaunchKernelGGL(k_cone_bp_direct, dim3((unsigned)(nbk * nbk * nbz)), dim3(256), 0, s, d,
+                           rs, v, nbk);
     INRCT_CHECK_LAUNCH();
 }
 

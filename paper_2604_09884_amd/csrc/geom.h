@@ -49,12 +49,40 @@ struct ConeView {
     int any_y, any_x;
 };
 
+// A tile of the LDS-staged cone projector: rays of view j, detector
+// columns [a0, a0 + kTileA) and rows [b0, b0 + kTileB) (clipped to the
+// detector), all with one principal axis.  Slices are visited in chunks of
+// kTileS aligned to multiples of kTileS; [slo, shi] holds every slice where
+// some ray of the tile has a tap inside the grid, [flo, fhi] (a sub-range)
+// every slice where some ray passes the FOV cylinder (all a projection of
+// an image that vanishes outside the FOV needs).  An empty range has
+// lo > hi.
+constexpr int kTileA = 64, kTileB = 24, kTileS = 8;
+struct ConeTile {
+    int j, a0, b0;
+    int slo, shi, flo, fhi;
+};
+
+// The adjoint works on blocks of kBpXY x kBpXY voxel columns.  For each
+// view and block: the detector columns [alo, alo + na) whose rays can touch
+// the block's voxels (central projection of the block's in-plane box widened
+// by one voxel, plus one column of margin), and the extremes of D_sd / d
+// over the box, d the depth along the view's central ray, from which the
+// rows touching a z band follow (row coordinate = z D_sd / d).
+constexpr int kBpXY = 16;
+struct BpCols {
+    int alo, na;
+    float kmin, kmax;
+};
+
 struct ConeDev {
     int N, V, Nu, Nv;
     double h, du;
     float dvf, cvf;        // row pitch and (Nv - 1)/2
     const ConeCol *col;    // [V][Nu]
     const ConeView *view;  // [V]
+    const BpCols *bpc;     // [V][nb][nb], nb = ceil(N / kBpXY)
+    const float *zeros;    // 64 zero floats (the source of staged taps outside the grid)
 };
 
 }  // namespace inrct
@@ -66,9 +94,15 @@ struct inrct_geom {
     std::vector<double> angles;
     inrct::DevBuf cols, steps, views, q, partials;
     int n_partials = 0;
-    // cone beam
-    inrct::DevBuf ccols, cviews, ut;
-    bool any_x = false;
+    // cone beam: per-column records, per-view records, and the projector's
+    // tile lists (LDS-staged tiles by principal axis, then the tiles that
+    // fall back to direct gathers)
+    inrct::DevBuf ccols, cviews, tiles, bpcols, zeros;
+    // 2D: transposed copy of the image for the x-principal rays
+    inrct::DevBuf ut;
+    int n_tile_y = 0, n_tile_x = 0, n_tile_f = 0;
+    bool bp_lds = false;  // every adjoint footprint fits the LDS caps
+    bool bp_w2 = false;   // and rows lie 1/2 to 1 voxel apart: the branch-free walk
     inrct::GeomDev dev() const {
         inrct::GeomDev d;
         d.kind = g.kind;
@@ -96,6 +130,8 @@ struct inrct_geom {
         d.cvf = 0.5f * (float)(g.n_v - 1);
         d.col = ccols.as<inrct::ConeCol>();
         d.view = cviews.as<inrct::ConeView>();
+        d.bpc = bpcols.as<inrct::BpCols>();
+        d.zeros = zeros.as<float>();
         return d;
     }
     int64_t m() const { return (int64_t)g.n_views * g.n_v * g.n_u; }
@@ -106,7 +142,10 @@ void cone_build(inrct_geom *h, Arena &a);
 void check_geom_args(const ct_geometry *g, const inr_grid *grid);
 inrct_geom *fresh_geom(const ct_geometry *g, const inr_grid *grid);
 void build_geom(inrct_geom *h, Arena &ar);
-void cone_project(inrct_geom *h, const float *u, float *z, hipStream_t s);
+void cone_project(inrct_geom *h, const float *u, float *z, bool fov_only, hipStream_t s);
+// z = P u; with fov_only the caller guarantees u = 0 outside the FOV (the
+// projector may then skip slices that lie outside it).
+void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov_only = false);
 void cone_backproject(inrct_geom *h, const float *r, float *v, hipStream_t s);
 void cone_backproject_at(inrct_geom *h, const float *r, const int32_t *idx, int64_t k,
                          float *out, hipStream_t s);

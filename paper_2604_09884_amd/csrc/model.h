@@ -93,7 +93,6 @@ void model_adam(inrct_model *m, float *theta, float *mm, float *vv, const float 
 int64_t geom_rays(const inrct_geom *g);
 int geom_dim(const inrct_geom *g);
 int geom_N(const inrct_geom *g);
-void project(inrct_geom *geom, const float *u, float *z, hipStream_t s);
 void backproject(inrct_geom *geom, const float *r, float *v, hipStream_t s);
 void backproject_at(inrct_geom *geom, const float *r, const int32_t *idx, int64_t k,
                     float *out, hipStream_t s);

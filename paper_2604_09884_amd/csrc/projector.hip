@@ -374,7 +374,7 @@ int64_t geom_rays(const inrct_geom *g) { return g->m(); }
 int geom_dim(const inrct_geom *g) { return g->dim; }
 int geom_N(const inrct_geom *g) { return g->N; }
 
-void project(inrct_geom *geom, const float *u, float *z, hipStream_t s) {
+void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov_only) {
     const GeomDev d = geom->dev();
     if (d.kind == INRCT_PAR2D || d.kind == INRCT_FAN2D) {
         float *ut = geom->ut.as<float>();
@@ -385,7 +385,7 @@ void project(inrct_geom *geom, const float *u, float *z, hipStream_t s) {
                            0, s, d, u, ut, z);
         INRCT_CHECK_LAUNCH();
     } else {
-        cone_project(geom, u, z, s);
+        cone_project(geom, u, z, fov_only, s);
     }
 }
 

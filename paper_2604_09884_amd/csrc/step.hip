@@ -512,7 +512,7 @@ static void grad_step(inr_ctx *c, uint64_t step, inrct_geom *geom, const float *
     model_eval_fov(m, c->theta, c->B, u, s);
     mark(0, 1);
     mark(1, 0);
-    project(geom, u, r, s);
+    project(geom, u, r, s, true);  // u vanishes outside the FOV
     mark(1, 1);
     // step 2: r = dL/dz, v = P^T r
     mark(2, 0);

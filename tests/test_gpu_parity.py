@@ -30,6 +30,18 @@ def _problems():
         ("par2d-ragged", configs.par2d_problem(37, 7, 53)),
         ("cone-small", configs.cone_problem(24, 5, 20).with_(n_v=18, dv=3.1 / 18)),
         ("cone-ragged", configs.cone_problem(19, 3, 70).with_(n_v=9, dv=3.1 / 9)),
+        # detector rows 0.68 voxel apart along z: the adjoint's branch-free
+        # two-rows-per-voxel walk
+        ("cone-w2", configs.cone_problem(40, 5, 60)),
+        # views at 45 degree multiples: tiles whose columns change principal
+        # axis take the direct-gather route
+        ("cone-45deg", configs.cone_problem(26, 8, 36).with_(n_v=20, dv=3.1 / 20)),
+        # detector pixels several voxels wide: footprints beyond the LDS
+        # capacity take the direct-gather route
+        ("cone-coarse", configs.cone_problem(80, 3, 12).with_(n_v=40, dv=3.1 / 40)),
+        # detector pixels a small fraction of a voxel: adjoint footprints
+        # beyond the LDS capacity read the residual in place
+        ("cone-fine", configs.cone_problem(16, 3, 200).with_(n_v=120, dv=3.1 / 120)),
         ("fan-small", configs.fan2d_problem(32, 12, 45)),
         ("fan-ragged", configs.fan2d_problem(37, 7, 53)),
         ("fan-wide", configs.fan2d_problem(41, 9, 61, du=5.0 / 61)),
