@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c4")
     ap.add_argument("--v-mode", default="full", choices=["full", "at_i"])
+    ap.add_argument("--loss", default="ls", choices=["ls", "fls"],
+                    help="data term: least squares, or the ramp-filtered FLS loss")
     ap.add_argument("--mlp-dtype", default=None, choices=[None, "bf16", "fp32"])
     ap.add_argument("--subsets", type=int, default=1,
                     help="ordered subsets over views: step t takes the loss over views j "
@@ -50,6 +52,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=2.0, help="arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=8,
                     help="requests resident and stepping at once")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="with --serve-compare: run only the comparison, not the stream")
     ap.add_argument("--serve-compare", type=int, default=0, metavar="Q",
                     help="with --serve: also the first Q requests in FP32 one at a time "
                          "against BF16 served together, with every request's final image MSE")
@@ -147,24 +151,45 @@ def cpu_baseline(p, target_s):
     }
 
 
-def e_kernel_traffic():
-    """HBM bytes per launch of the grid-evaluation kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
-    changed since those counters were taken."""
+PROFILE_SOURCES = {
+    "mlp": os.path.join("paper_2604_09884_amd", "csrc", "mlp.hip"),
+    "cone": os.path.join("paper_2604_09884_amd", "csrc", "cone.hip"),
+}
+
+
+def profile_figures(name):
+    """Per-kernel figures (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE,
+    VALU busy and matrix-core utilisation) from the JSON block of a committed
+    counter summary under profiles/, keeping only the kernels whose source
+    file still hashes to the value recorded with the counters."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "step_c4_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2604_09884_amd", "csrc", "mlp.hip")
     try:
-        text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        text = open(os.path.join(ROOT, "profiles", name)).read()
     except OSError:
-        return None
-    m_sha = re.search(r"source sha256: ([0-9a-f]{64})", text)
-    m_b = re.search(r"traffic bytes per launch: (\d+)", text)
-    if not m_sha or not m_b or m_sha.group(1) != sha:
-        return None
-    return int(m_b.group(1))
+        return {}
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return {}
+    data = json.loads(m.group(1))
+    shas = {}
+    for key, rel in PROFILE_SOURCES.items():
+        try:
+            shas[key] = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()
+        except OSError:
+            shas[key] = None
+    out = {}
+    for kernel, rec in data.get("kernels", {}).items():
+        src = rec.get("source")
+        if src in shas and rec.get("sha256") == shas[src]:
+            out[kernel] = rec
+    return out
+
+
+def _fig(figs, kernels, field):
+    """Sum (bytes) of a field over kernels, or None if any is missing."""
+    vals = [figs.get(k, {}).get(field) for k in kernels]
+    return None if any(v is None for v in vals) else sum(vals)
 
 
 def _sinograms(probs):
@@ -218,7 +243,12 @@ def _serve(probs, ys, arrivals, dtype, n_slots, depth=2):
     for i in ids:  # arrival times count from the start of the run
         if arrivals is None:
             srv.slots[i].t_arrive = 0.0
-    srv.run()
+
+    def progress(sv):
+        m = sv.metrics()
+        log("  t %.0f s: %d done, %d active, %d queued, %d steps"
+            % (sv.now(), m["done"], len(sv.active()), len(sv.queue), m["steps"]))
+    srv.run(progress=progress)
     torch.cuda.synchronize()
     return srv, ids
 
@@ -252,11 +282,16 @@ def serve_bench(a):
             seen.add(key)
             warm.append((p.with_(steps=1), y))
     _serve([w[0] for w in warm], [w[1] for w in warm], None, "bf16", a.serve_slots)
-    srv, ids = _serve(probs, ys, arrivals, "bf16", a.serve_slots)
-    m = srv.metrics()
-    bad = [srv.status(i).error for i in ids if srv.status(i).state != DONE]
-    log("served: %s%s" % ({k: round(v, 3) if isinstance(v, float) else v
-                           for k, v in m.items()}, " failures %s" % bad if bad else ""))
+    if a.no_stream:
+        m = {k_: None for k_ in ("latency_s_p50", "latency_s_p95", "latency_s_p99",
+                                 "latency_s_max", "queue_wait_s_p50", "queue_wait_s_p99",
+                                 "steps_per_s", "makespan_s", "done", "failed")}
+    else:
+        srv, ids = _serve(probs, ys, arrivals, "bf16", a.serve_slots)
+        m = srv.metrics()
+        bad = [srv.status(i).error for i in ids if srv.status(i).state != DONE]
+        log("served: %s%s" % ({k: round(v, 3) if isinstance(v, float) else v
+                               for k, v in m.items()}, " failures %s" % bad if bad else ""))
     out = {
         "metric": "p99 recon latency (served mixed 2D/3D stream)",
         "value": m["latency_s_p99"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
@@ -330,7 +365,9 @@ def main():
     geom = ops.Geometry(p)
     k = p.k(model.n_fov)
     v_mode = L.INRCT_V_FULL if a.v_mode == "full" else L.INRCT_V_AT_I
-    st = ops.GradStepper(model, geom, th, Bd, yd, k, p.lr, seed=p.seed_sampler, v_mode=v_mode)
+    loss_kind = L.INRCT_FLS if a.loss == "fls" else L.INRCT_LS
+    st = ops.GradStepper(model, geom, th, Bd, yd, k, p.lr, seed=p.seed_sampler, v_mode=v_mode,
+                         loss=loss_kind)
     stepper = ops.OrderedSubsets(st, a.subsets) if a.subsets > 1 else st
     torch.cuda.synchronize()
     free1, _ = torch.cuda.mem_get_info()
@@ -368,7 +405,7 @@ def main():
     if a.v_mode == "full" and a.subsets == 1:
         th2 = torch.tensor(theta, dtype=torch.float32, device=dev)
         st2 = ops.GradStepper(model, geom, th2, Bd, yd, k, p.lr, seed=p.seed_sampler,
-                              v_mode=L.INRCT_V_AT_I)
+                              v_mode=L.INRCT_V_AT_I, loss=loss_kind)
         for t in range(a.warmup):
             st2.step(t)
         st2.enable_timing(max(1, a.steps))
@@ -385,28 +422,79 @@ def main():
         log("v at I: %.2f ms/step (P^T at I %.3f ms)" % (ms2, alt["backproject_ms"]))
         st2.close()
 
-    traffic = e_kernel_traffic() if a.config == "c4" and dtype == "bf16" else None
-    if p.arch.kind == "hash":
-        traffic = None
+    figs = {}
+    if a.config == "c4" and dtype == "bf16" and a.subsets == 1:
+        figs.update(profile_figures("step_c4_hbm_traffic.md"))
+        util = profile_figures("step_c4_utilization.md")
+        for k_, rec in util.items():
+            figs.setdefault(k_, {}).update(rec)
+    e_kernel = "k_hash_eval" if p.arch.kind == "hash" else "k_eval_lds_w"
+    traffic = _fig(figs, [e_kernel], "traffic_bytes")
     flop_per_point = p.arch.flops_forward()
     if p.arch.kind == "hash":  # plus the interpolation: 2^d weights x 2 features per level
         flop_per_point += p.arch.hash_levels * (1 << p.dim) * 2 * 2
     e_ms = stages["eval_grid"] / a.steps
     achieved = model.n_fov * flop_per_point / (e_ms * 1e-3)
     hashed = p.arch.kind == "hash"
+    # a gather-latency kernel in FP32 vector arithmetic without packed
+    # instructions: peak 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s
+    peak = 78.6e12 if hashed else PEAK[dtype]
     roofline = {"bound": "alu" if hashed else "mfma",
-                "kernel": ("k_hash_eval" if hashed else "k_eval_lds_w") + " (grid evaluation E)",
-                "achieved": achieved / 1e12, "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[dtype], "traffic": traffic,
+                "kernel": e_kernel + " (grid evaluation E)",
+                "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated; "
                                 "profiles/step_c4_hbm_traffic.md)",
                 "per_unit": "%d FLOP per FOV point x %d points per launch"
                             % (flop_per_point, model.n_fov),
                 "avg_launch_ms": e_ms}
+    mfma_util = _fig(figs, [e_kernel], "mfma_util")
+    if mfma_util is not None:
+        roofline["mfma_busy_counter"] = mfma_util
+    stage_roofs = None
+    if p.dim == 3:
+        n_grid = p.N ** 3
+        m_rays = geom.n_rays
+        p_ms = stages["project"] / a.steps
+        pt_ms = stages["backproject"] / a.steps
+        v_ms = stages["vjp"] / a.steps
+        p_bytes = p.n_views * model.n_fov * 4 + m_rays * 4
+        pt_bytes = m_rays * 4 + n_grid * 4
+        p_kernels = ["k_cone_fwd_lds<true>", "k_cone_fwd_lds<false>"]
+        pt_kernels = ["k_cone_prescale", "k_cone_bp_lds<true>"]
+        p_traffic = _fig(figs, p_kernels, "traffic_bytes")
+        pt_traffic = _fig(figs, pt_kernels, "traffic_bytes")
+        vjp_flop = p.arch.flops_vjp() * k  # forward recompute + dW + delta, per sample
+        stage_roofs = {
+            "P": {"kernels": p_kernels, "ms": p_ms, "bound": "alu",
+                  "hbm_alg_bytes": p_bytes,
+                  "hbm_alg_note": "view-major model: every view reads the FOV volume once "
+                                  "(%d x %d x 4 B) and writes its rays (%d x 4 B)"
+                                  % (p.n_views, model.n_fov, m_rays),
+                  "hbm_alg_frac": p_bytes / (p_ms * 1e-3) / 8e12,
+                  "traffic": p_traffic,
+                  "hbm_counter_frac": (None if p_traffic is None
+                                       else p_traffic / (p_ms * 1e-3) / 8e12),
+                  "valu_busy_counter": _fig(figs, p_kernels[:1], "valu_busy"),
+                  "valu_busy_counter_x": _fig(figs, p_kernels[1:], "valu_busy")},
+            "PT": {"kernels": pt_kernels, "ms": pt_ms, "bound": "alu",
+                   "hbm_alg_bytes": pt_bytes,
+                   "hbm_alg_note": "the residual read once, v written once",
+                   "hbm_alg_frac": pt_bytes / (pt_ms * 1e-3) / 8e12,
+                   "traffic": pt_traffic,
+                   "hbm_counter_frac": (None if pt_traffic is None
+                                        else pt_traffic / (pt_ms * 1e-3) / 8e12),
+                   "valu_busy_counter": _fig(figs, pt_kernels[1:], "valu_busy")},
+            "VJP": {"ms": v_ms, "bound": "mfma", "flop": vjp_flop,
+                    "achieved_tflops": vjp_flop / (v_ms * 1e-3) / 1e12,
+                    "frac": vjp_flop / (v_ms * 1e-3) / PEAK[dtype],
+                    "traffic": _fig(figs, ["k_vjp_w", "k_dw_gemm2"], "traffic_bytes")},
+        }
     out = {
         "metric": ("grad steps/s at 501^3 cone-beam 20 views" if a.config == "c4"
                    else "grad steps/s at " + p.name)
-                  + (" (%d ordered subsets)" % a.subsets if a.subsets > 1 else ""),
+                  + (" (%d ordered subsets)" % a.subsets if a.subsets > 1 else "")
+                  + (" (FLS loss)" if a.loss == "fls" else ""),
         "value": 1e3 / ms_step,
         "unit": "steps/s",
         "n_gpus": 1,
@@ -423,7 +511,8 @@ def main():
         "config": {"workload": p.name, "grid": "%d^%d" % (p.N, p.dim),
                    "views": p.n_views, "detector": "%dx%d" % (p.n_v, p.n_u),
                    "n_fov": model.n_fov, "k": k, "params": model.n_params,
-                   "v_mode": a.v_mode, "subsets": a.subsets, "parallelism": "single GPU"},
+                   "v_mode": a.v_mode, "subsets": a.subsets, "loss": a.loss,
+                   "parallelism": "single GPU"},
         "stages_ms_per_step": {k_: v / a.steps for k_, v in stages.items()},
         "device_mem_gb": (free0 - free1) / 1e9,
         # the library allocates only when handles are created, so the
@@ -432,6 +521,8 @@ def main():
         "loss_last": loss,
         "roofline": roofline,
     }
+    if stage_roofs is not None:
+        out["roofline_stages"] = stage_roofs
     if alt is not None:
         out["v_at_I"] = alt
     if not a.no_cpu:

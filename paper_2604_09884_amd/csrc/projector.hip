@@ -335,30 +335,44 @@ __global__ __launch_bounds__(256) void k_diff(const float *__restrict__ z,
 }
 
 // r = F q along each detector row (Ram-Lak, linear convolution), and the
-// per-block partials of 1/2 q.r.  Row length nu, rows = m / nu.
-__global__ __launch_bounds__(256) void k_ramp(const float *__restrict__ q, float *r,
-                                              int nu, int64_t rows, double du,
-                                              double *partials) {
+// per-block partials of 1/2 q.r.  Row length nu, rows = m / nu.  A block
+// takes rows blockIdx.x, blockIdx.x + gridDim.x, ...: the row is staged in
+// LDS between nu zeros on each side (so no tap needs a bounds test) and the
+// odd taps f_j = -1 / (pi^2 j^2 du) are computed once per block; each
+// output sums its taps in increasing j.  LDS: 3 nu + nu / 2 floats.
+__global__ __launch_bounds__(256) void k_ramp(const float *__restrict__ q, float *r, int nu,
+                                              int64_t rows, double du, double *partials) {
+    extern __shared__ float lds[];
+    float *row = lds;               // [3 nu]: zeros, the row, zeros
+    float *tap = lds + 3 * nu;      // [nu / 2]: f_{2i+1}
     __shared__ double sh[256];
-    double acc = 0.0;
-    const int64_t m = rows * nu;
     const float f0 = (float)(1.0 / (4.0 * du));
     const float cf = (float)(-1.0 / (M_PI * M_PI * du));
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += stride) {
-        const int64_t row = i / nu;
-        const int a = (int)(i - row * nu);
-        const float *qr = q + row * nu;
-        float s = f0 * qr[a];
-        // odd offsets only: f_j = -1/(pi^2 j^2 du)
-        for (int jj = 1; jj < nu; jj += 2) {
-            float t = 0.f;
-            if (a - jj >= 0) t += qr[a - jj];
-            if (a + jj < nu) t += qr[a + jj];
-            s += cf / ((float)jj * (float)jj) * t;
+    const int nt = nu / 2;          // odd offsets 1, 3, ..., < nu
+    for (int i = threadIdx.x; i < nt; i += 256) {
+        const int jj = 2 * i + 1;
+        tap[i] = cf / ((float)jj * (float)jj);
+    }
+    for (int i = threadIdx.x; i < nu; i += 256) {
+        row[i] = 0.f;
+        row[2 * nu + i] = 0.f;
+    }
+    double acc = 0.0;
+    for (int64_t rw = blockIdx.x; rw < rows; rw += gridDim.x) {
+        const float *qr = q + rw * nu;
+        __syncthreads();  // the previous row's reads are done
+        for (int i = threadIdx.x; i < nu; i += 256) row[nu + i] = qr[i];
+        __syncthreads();
+        for (int a = threadIdx.x; a < nu; a += 256) {
+            const float *c = row + nu + a;
+            float s = f0 * c[0];
+            for (int i = 0; i < nt; ++i) {
+                const int jj = 2 * i + 1;
+                s += tap[i] * (c[-jj] + c[jj]);
+            }
+            r[rw * nu + a] = s;
+            acc += 0.5 * (double)c[0] * (double)s;
         }
-        r[i] = s;
-        acc += 0.5 * (double)qr[a] * (double)s;
     }
     const double tot = block_sum_f64(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -444,8 +458,9 @@ void residual_loss(inrct_geom *geom, int loss, const float *z, const float *y,
         hipLaunchKernelGGL(k_diff, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, z, y,
                            q, m);
         INRCT_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_ramp, dim3(nb), dim3(256), 0, s, q, r, geom->g.n_u,
-                           m / geom->g.n_u, geom->g.du, part);
+        const int nu = geom->g.n_u;
+        hipLaunchKernelGGL(k_ramp, dim3(nb), dim3(256), sizeof(float) * (3 * nu + nu / 2), s, q,
+                           r, nu, m / nu, geom->g.du, part);
         INRCT_CHECK_LAUNCH();
     }
     if (loss_out) launch_sum_partials(part, nb, loss_out, s);
@@ -460,6 +475,8 @@ void check_geom_args(const ct_geometry *g, const inr_grid *grid) {
     INRCT_REQUIRE(g->n_views >= 1 && g->n_u >= 1 && g->n_v >= 1, "empty detector");
     INRCT_REQUIRE(g->angles != nullptr, "angles must be a host array");
     INRCT_REQUIRE(g->du > 0 && g->dv > 0, "detector pitch must be positive");
+    // the FLS filter stages a detector row (3.5 n_u floats) in 64 KB of LDS
+    INRCT_REQUIRE(g->n_u <= 4096, "detector rows are limited to 4096 bins");
     if (g->kind == INRCT_PAR2D) {
         INRCT_REQUIRE(grid->dim == 2, "PAR2D needs a 2D grid");
         INRCT_REQUIRE(g->n_v == 1, "PAR2D needs n_v == 1");

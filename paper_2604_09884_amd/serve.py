@@ -328,14 +328,20 @@ class Server:
         self.ticks += 1
         return busy
 
-    def run(self, max_ticks: Optional[int] = None, idle_sleep: float = 2e-4):
+    def run(self, max_ticks: Optional[int] = None, idle_sleep: float = 2e-4,
+            progress=None, every: float = 10.0):
         """Runs until every submitted request has ended.  Waits for future
-        arrivals on the server clock."""
+        arrivals on the server clock.  `progress(server)` is called about
+        every `every` seconds of the server clock."""
         n = 0
+        t_next = self.now() + every
         while not self.idle() and (max_ticks is None or n < max_ticks):
             if not self.tick():
                 time.sleep(idle_sleep)
             n += 1
+            if progress is not None and self.now() >= t_next:
+                progress(self)
+                t_next = self.now() + every
 
     # ---- metrics
     def metrics(self) -> dict:

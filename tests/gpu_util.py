@@ -10,6 +10,15 @@ def say(*a):
     sys.stdout.flush()
 
 
+def report(workload, dtype, quantity, value, tol=None):
+    """Prints one measured error against the FP64 oracle as a JSON line
+    (the table of errors per result is collected from these lines)."""
+    import json
+    say("ERROR-REPORT " + json.dumps({"workload": workload, "dtype": dtype,
+                                      "quantity": quantity, "value": float(value),
+                                      "tolerance": tol}))
+
+
 def rel(a, b):
     a = np.asarray(a, np.float64).ravel()
     b = np.asarray(b, np.float64).ravel()

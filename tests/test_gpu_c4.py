@@ -11,7 +11,7 @@ from oracle import inr as oinr
 from oracle import joseph
 from oracle import sampler as osampler
 from paper_2604_09884_amd import configs, synth
-from tests.gpu_util import dev, host, rel, say
+from tests.gpu_util import dev, host, rel, report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,7 @@ def test_c4_projection_sampled_rays(geom):
         got.append(z[j][np.ix_(rows, cols)].ravel())
     e = rel(np.concatenate(got), np.concatenate(ref))
     say("C4 sampled-ray P rel", e)
+    report("cone3d-501 (C4)", "fp32", "P, sampled rays", e, 1e-5)
     assert e <= 1e-5
 
 
@@ -105,6 +106,7 @@ def test_c4_backprojection_sampled_voxels(geom):
     ref = np.array([_window_adjoint(int(q), r3, N) for q in vox])
     e = rel(v[vox], ref)
     say("C4 sampled-voxel P^T rel", e)
+    report("cone3d-501 (C4)", "fp32", "P^T, sampled voxels", e, 1e-5)
     assert e <= 1e-5
     va = host(ops.ct_backproject_at(geom, dev(r), dev(vox, torch.int32)))
     assert np.allclose(va, v[vox], rtol=1e-6, atol=1e-6 * np.abs(v).max())
@@ -118,6 +120,7 @@ def test_c4_adjoint_identity(geom):
     v = host(ops.ct_backproject(geom, dev(r))).ravel()
     lhs, rhs = float(z @ r), float(u.astype(np.float64) @ v)
     say("C4 <Pu,r> - <u,P^T r> relative", abs(lhs - rhs) / (np.linalg.norm(z) * np.linalg.norm(r)))
+    report("cone3d-501 (C4)", "fp32", "adjoint identity <Pu,r> - <u,P^T r>", abs(lhs - rhs) / (np.linalg.norm(z) * np.linalg.norm(r)), 1e-5)
     assert abs(lhs - rhs) <= 1e-6 * np.linalg.norm(z) * np.linalg.norm(r)
 
 
@@ -135,6 +138,7 @@ def test_c4_grid_evaluation_sampled_points():
     ref = oinr.forward(theta, B, ogrid.coords(3, N, pts), arch)
     e = rel(u[pts], ref)
     say("C4 E (bf16) sampled rel", e)
+    report("cone3d-501 (C4)", "bf16", "E, sampled points", e, 2e-2)
     assert e <= 2e-2
     # outside the FOV the grid is zero
     outside = np.array([0, N - 1, N * N - 1, N * N * (N - 1)])

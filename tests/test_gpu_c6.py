@@ -13,7 +13,7 @@ from oracle import inr as oinr
 from oracle import joseph
 from oracle import sampler as osampler
 from paper_2604_09884_amd import configs, synth
-from tests.gpu_util import dev, host, rel, say
+from tests.gpu_util import dev, host, rel, report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,7 @@ def test_c6_projection_sampled_views(geom):
         got.append(z[j])
     e = rel(np.concatenate(got), np.concatenate(ref))
     say("C6 sampled-view P rel", e)
+    report("fan2d-512 (C6)", "fp32", "P, sampled views", e, 1e-5)
     assert e <= 1e-5
 
 
@@ -64,6 +65,7 @@ def test_c6_backprojection_sampled_pixels(geom):
                     for q in pix])
     e = rel(v[pix], ref)
     say("C6 sampled-pixel P^T rel", e)
+    report("fan2d-512 (C6)", "fp32", "P^T, sampled pixels", e, 1e-5)
     assert e <= 1e-5
     va = host(ops.ct_backproject_at(geom, dev(r), dev(pix, torch.int32)))
     assert np.allclose(va, v[pix], rtol=1e-6, atol=1e-6 * np.abs(v).max())
@@ -93,6 +95,7 @@ def test_c6_grid_evaluation_and_sampler():
     pts = np.unique(np.concatenate([fov[RNG(26).choice(fov.size, 4000)], [fov[0], fov[-1]]]))
     e = rel(u[pts], oinr.forward(theta, B, ogrid.coords(2, N, pts), arch))
     say("C6 E (bf16) sampled rel", e)
+    report("fan2d-512 (C6)", "bf16", "E, sampled points", e, 2e-2)
     assert e <= 2e-2
     assert np.all(u[np.setdiff1d(np.arange(N * N), fov)] == 0)
     got = host(ops.sample(m, P6.seed_sampler, 11, k)).astype(np.int64)

@@ -9,7 +9,7 @@ from oracle import inr as oinr
 from oracle import sampler as osampler
 from oracle import step as ostep
 from paper_2604_09884_amd import configs, synth
-from tests.gpu_util import dev, host, rel, say
+from tests.gpu_util import dev, host, rel, report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -113,6 +113,7 @@ def test_hash_full_size_sampled():
                                     [fov[0], fov[-1]]]))
     e = rel(u[pts], oinr.forward(theta, None, ogrid.coords(2, N, pts), arch))
     say("C7 E sampled rel", e)
+    report("fan2d-512-hash (C7)", "fp32", "E, sampled points", e, 1e-4)
     assert e <= 1e-4
     keep = _away_from_kinks(theta, arch, ogrid.coords(2, N, pts), 1e-4)
     idx = pts[keep][:2000]
@@ -121,6 +122,7 @@ def test_hash_full_size_sampled():
                                     v_compact=True))
     g_ref = oinr.vjp(theta, None, ogrid.coords(2, N, idx), 3.0 * v, arch)
     say("C7 g rel", rel(g, g_ref))
+    report("fan2d-512-hash (C7)", "fp32", "g", rel(g, g_ref), 1e-4)
     assert rel(g, g_ref) <= 1e-4
 
 

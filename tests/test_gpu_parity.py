@@ -12,7 +12,7 @@ from oracle import grid as ogrid
 from oracle import inr as oinr
 from oracle import joseph, loss as oloss, sampler as osampler, adam as oadam
 from paper_2604_09884_amd import configs, synth
-from tests.gpu_util import dev, host, rel, say
+from tests.gpu_util import dev, host, rel, report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +60,8 @@ def test_project_and_backproject_match_oracle(name, p):
     v = host(ops.ct_backproject(g, dev(r)))
     ez, ev = rel(z, P @ u), rel(v, P.T @ r)
     say(name, "P rel", ez, "P^T rel", ev)
+    report(name, "fp32", "P", ez, 1e-5)
+    report(name, "fp32", "P^T", ev, 1e-5)
     assert ez <= 1e-5 and ev <= 1e-5
     # adjoint identity of the GPU pair, dot products in float64
     zz = host(ops.ct_project(g, dev(u)))
@@ -129,6 +131,7 @@ def test_eval_and_vjp_match_oracle(name, arch, prob, dtype):
     tol = 1e-4 if dtype == "fp32" else 2e-2
     eu = rel(u, u_ref)
     say(name, dtype, "E rel", eu)
+    report(name + " (INR only)", dtype, "E", eu, tol)
     assert eu <= tol
     assert np.all(u.ravel()[np.setdiff1d(np.arange(N ** dim), fov)] == 0)
     # Eq. (2) on a ragged subset with the cotangent of Algorithm 1:
@@ -143,6 +146,7 @@ def test_eval_and_vjp_match_oracle(name, arch, prob, dtype):
     g_ref = oinr.vjp(theta, B, ogrid.coords(dim, N, idx), scale * v_alg[idx], arch)
     eg = rel(g, g_ref)
     say(name, dtype, "g rel (Algorithm-1 cotangent)", eg)
+    report(name + " (INR only)", dtype, "g, Algorithm-1 cotangent", eg, tol)
     assert eg <= tol
     # compact v gives the same result
     g2 = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(v_alg[idx]), scale,

@@ -7,7 +7,7 @@ from oracle import adam as oadam
 from oracle import sampler as osampler
 from oracle import step as ostep
 from paper_2604_09884_amd import configs, synth
-from tests.gpu_util import dev, host, rel, say
+from tests.gpu_util import dev, host, rel, report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +36,10 @@ def test_single_step_c1(v_mode):
     g_ref, L_ref, *_ = ostep.grad_estimate(prob, theta, B, y.astype(np.float64), idx)
     g = host(st.buffer(3, st.model.n_params))
     say("c1 loss", host(st.loss), L_ref, "g rel", rel(g, g_ref))
+    report("par2d-128-ffn (C1) step, v %s" % ("full" if v_mode == 0 else "at I"), "fp32", "g",
+           rel(g, g_ref), 1e-4)
+    report("par2d-128-ffn (C1) step, v %s" % ("full" if v_mode == 0 else "at I"), "fp32",
+           "loss", abs(host(st.loss) - L_ref) / L_ref, 1e-5)
     assert abs(host(st.loss) - L_ref) <= 1e-5 * L_ref
     assert rel(g, g_ref) <= 1e-4
     th_ref, _, _ = oadam.adam_update(theta, np.zeros_like(theta), np.zeros_like(theta),
@@ -53,6 +57,8 @@ def test_subsampled_step_small_cone():
     g_ref, L_ref, *_ = ostep.grad_estimate(prob, theta, B, y.reshape(-1).astype(np.float64), idx)
     g = host(st.buffer(3, st.model.n_params))
     say("cone loss", host(st.loss), L_ref, "g rel", rel(g, g_ref))
+    report("cone3d-20 step", "fp32", "g", rel(g, g_ref), 1e-4)
+    report("cone3d-20 step", "fp32", "loss", abs(host(st.loss) - L_ref) / L_ref, 1e-5)
     assert abs(host(st.loss) - L_ref) <= 1e-5 * L_ref
     assert rel(g, g_ref) <= 1e-4
 
@@ -70,6 +76,9 @@ def test_subsampled_step_small_fan():
                                                idx)
         g = host(st.buffer(3, st.model.n_params))
         say("fan", dtype, "loss", host(st.loss), L_ref, "g rel", rel(g, g_ref))
+        report("fan2d-40 step", dtype, "g", rel(g, g_ref), tol)
+        report("fan2d-40 step", dtype, "loss", abs(host(st.loss) - L_ref) / L_ref,
+               1e-5 if dtype == "fp32" else tol)
         assert abs(host(st.loss) - L_ref) <= (1e-5 if dtype == "fp32" else tol) * L_ref
         assert rel(g, g_ref) <= tol
         st.close()
@@ -91,4 +100,6 @@ def test_c1_fit_final_mse_within_2_percent():
     mse_gpu = ostep.mse(u_gpu, truth, prob.fov)
     mse_ref = ostep.mse(prob.E(th, B), truth, prob.fov)
     say("c1 20-step MSE gpu", mse_gpu, "oracle", mse_ref)
+    report("par2d-128-ffn (C1) 20-step fit", "fp32", "final MSE", abs(mse_gpu - mse_ref) / mse_ref,
+           0.02)
     assert abs(mse_gpu - mse_ref) <= 0.02 * mse_ref

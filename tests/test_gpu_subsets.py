@@ -96,3 +96,56 @@ def test_single_view_subsets_fan():
         assert rel(host(st.buffer(3, st.model.n_params)), g_ref) <= 1e-4
     os_.close()
     st.close()
+
+
+FFN2 = configs.INRArch("ffn", 2, 32, 10.0, 128, 3)
+FFN3 = configs.INRArch("ffn", 3, 32, 3.0, 128, 2)
+
+
+def _ffn_cases():
+    return [
+        ("par2d-ffn", configs.par2d_problem(40, 30, 57, arch=FFN2, k_frac=0.25, n_ellipses=5),
+         "ls"),
+        ("cone3d-ffn", configs.cone_problem(16, 10, 20, arch=FFN3, k_frac=0.1, n_ellipses=5),
+         "ls"),
+    ]
+
+
+@pytest.mark.parametrize("name,p,loss", _ffn_cases(), ids=[c[0] for c in _ffn_cases()])
+def test_ordered_subsets_ffn_match_oracle(name, p, loss):
+    # The ReLU network keeps every point.  A point whose oracle
+    # pre-activation lies within rounding of 0 at some unit may take the
+    # other ReLU branch in FP32; the test allows the GPU's g to differ from
+    # the oracle's by 1e-4 ||g|| plus twice the summed norms of those points'
+    # whole contributions, and by no more.
+    from oracle import grid as ogrid
+    from oracle import inr as oinr
+    from paper_2604_09884_amd import ops
+    st, B, y = _stepper(p, loss)
+    S = 3
+    os_ = ops.OrderedSubsets(st, S)
+    prob = ostep.Problem(p)
+    yv = y.reshape(-1).astype(np.float64)
+    for t in range(4):
+        th = host(st.theta).astype(np.float64)
+        os_.step(t)
+        sub, rows = ostep.subset_problem(prob, ostep.subset_views(p.n_views, S, t % S))
+        idx = osampler.sample_indices(prob.fov, st.k, p.seed_sampler, t)
+        g_ref, L_ref, _, _, _, v = ostep.grad_estimate(sub, th, B, yv[rows], idx, loss)
+        X = ogrid.coords(p.dim, p.N, idx)
+        _, _, pre = oinr.forward(th, B, X, p.arch, keep=True)
+        near = np.zeros(idx.size, bool)
+        for z in pre:
+            near |= np.any(np.abs(z) <= 2e-4 * np.sqrt(np.mean(z * z)), axis=1)
+        scale = prob.n / idx.size
+        slack = sum(np.linalg.norm(oinr.vjp(th, B, X[i:i + 1], scale * v[idx[i:i + 1]], p.arch))
+                    for i in np.nonzero(near)[0])
+        g = host(st.buffer(3, st.model.n_params))
+        dev_ = np.linalg.norm(g - g_ref)
+        say(name, "t", t, "loss", float(host(st.loss)), L_ref, "g rel", rel(g, g_ref),
+            "near-kink points", int(near.sum()), "of", idx.size,
+            "allowed", (1e-4 * np.linalg.norm(g_ref) + 2 * slack) / np.linalg.norm(g_ref))
+        assert abs(float(host(st.loss)) - L_ref) <= 1e-5 * abs(L_ref)
+        assert dev_ <= 1e-4 * np.linalg.norm(g_ref) + 2 * slack
+    os_.close()
+    st.close()

@@ -10,7 +10,7 @@ from oracle import grid as ogrid
 from oracle import inr as oinr
 from oracle import sampler as osampler
 from paper_2604_09884_amd import configs, synth
-from tests.gpu_util import dev, host, rel, say
+from tests.gpu_util import dev, host, rel, report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +73,7 @@ def test_vjp_fp32_across_chunks_c4_arch():
     g_ref = _oracle_vjp(theta, B, ogrid.coords(3, N, idx), 1.5 * v, arch)
     e = rel(g, g_ref)
     say("fp32 multi-chunk g rel", e)
+    report("ffn 3->512+5x256, %d points (2 chunks)" % k, "fp32", "g (VJP)", e, 1e-4)
     assert e <= 1e-4
     # linearity across chunks: the sum over I equals the sum of the halves
     h = k // 2
@@ -101,6 +102,7 @@ def test_vjp_bf16_width256_across_chunks():
     g_ref = _oracle_vjp(theta, B, X, 0.75 * v, arch)
     e = rel(g, g_ref)
     say("bf16 width-256 g rel over %d chunks (k %d)" % (-(-k // CHUNK), k), e)
+    report("ffn 3->512+5x256, %d points (4 chunks)" % k, "bf16", "g (VJP)", e, 2e-2)
     assert e <= 2e-2
     # the last, ragged chunk alone against its own oracle sum
     tail = slice(3 * CHUNK, k)
@@ -133,6 +135,7 @@ def test_vjp_at_the_501_cube_index_set():
     g_ref = _oracle_vjp(theta, B, X, scale * v, p.arch, block=100000)
     e = rel(g, g_ref)
     say("501^3 I: k %d, g rel %.3e (BF16, %d chunks)" % (k, e, -(-k // CHUNK)))
+    report("cone3d-501 (C4) index set, 987,757 points", "bf16", "g (VJP)", e, 2e-2)
     assert e <= 2e-2
 
 
@@ -175,4 +178,5 @@ def test_inr_function_virtual_loss_backward(case):
     g_ref = oinr.vjp(theta, B, X, (n / k) * v, p.arch)
     eg = rel(g, g_ref)
     say("INRFunction %s: |I| %d of n %d, f rel %.3e, g rel %.3e" % (case, k, n, ef, eg))
+    report("INRFunction %s" % case, dtype, "g (virtual-loss backward)", eg, tol)
     assert ef <= tol and eg <= tol
