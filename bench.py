@@ -428,7 +428,8 @@ def main():
         util = profile_figures("step_c4_utilization.md")
         for k_, rec in util.items():
             figs.setdefault(k_, {}).update(rec)
-    e_kernel = "k_hash_eval" if p.arch.kind == "hash" else "k_eval_lds_w"
+    e_kernel = ("k_hash_eval" if p.arch.kind == "hash"
+                else "k_eval_lds_w<%d>" % (1 if p.arch.kind == "ffn" else 2))
     traffic = _fig(figs, [e_kernel], "traffic_bytes")
     flop_per_point = p.arch.flops_forward()
     if p.arch.kind == "hash":  # plus the interpolation: 2^d weights x 2 features per level
