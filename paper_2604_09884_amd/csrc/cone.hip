@@ -636,7 +636,7 @@ __device__ __forceinline__ void cone_cols(const ConeDev &g, const ConeView &vg, 
     const float u1 = (ax * D1y - ay * D1x) * __builtin_amdgcn_rcpf(eux * D1y - euy * D1x);
     const float u2 = (ax * D2y - ay * D2x) * __builtin_amdgcn_rcpf(eux * D2y - euy * D2x);
     const float c = 0.5f * (float)(g.Nu - 1);
-    const float a1 = u1 / (float)g.du + c, a2 = u2 / (float)g.du + c;
+    const float a1 = fmaf(u1, g.inv_du, c), a2 = fmaf(u2, g.inv_du, c);
     // the columns inside [a1, a2], widened by the margin
     float l = ceilf(fminf(a1, a2) - 0.01f), r = floorf(fmaxf(a1, a2) + 0.01f);
     l = fmaxf(l, 0.f);
@@ -752,9 +752,12 @@ __device__ __forceinline__ void cone_gather_view_w2(const ConeDev &g, const Cone
             const float wo = io == o ? 1.f - fo : fo;
             const long long E0 = c.Z0 + (long long)s * c.D0;
             const long long E1 = c.Z1 + (long long)s * c.D1;
-            // the first row whose stencil reaches z0 - 1: estimate, then exact
+            // the first row whose stencil reaches z0 - 1: an estimate from
+            // the high bits (E1 >= 2^39, so E1 >> 24 keeps 16 bits and the
+            // estimate is within a tenth of a row), then exact
             const long long lo_t = (long long)(z0 - 1) * (1LL << 40);
-            int b = (int)floorf((float)(lo_t - E0) * __builtin_amdgcn_rcpf((float)E1));
+            int b = (int)floorf((float)(int)((lo_t - E0) >> 24) *
+                                __builtin_amdgcn_rcpf((float)(int)(E1 >> 24)));
             long long ph = E0 + (long long)b * E1;
             if (ph >= lo_t) {
                 --b;
@@ -773,12 +776,15 @@ __device__ __forceinline__ void cone_gather_view_w2(const ConeDev &g, const Cone
             // (1 - w) to voxel jz and w to voxel jz + 1
 #pragma unroll
             for (int jz = -1; jz < ZC; ++jz) {
+                // both rows are read unconditionally (R holds the row after
+                // the last), so a band is straight-line code
+                const float rA = R[ri], rB = R[ri + rstride];
                 const float wA = fx40_frac(ph);
-                const float tA = wo * R[ri];
+                const float tA = wo * rA;
                 const long long phB = ph + E1;
                 const bool inB = fx40_int(phB) == z0 + jz;
                 const float wB = fx40_frac(phB);
-                const float tB = inB ? wo * R[ri + rstride] : 0.f;
+                const float tB = inB ? wo * rB : 0.f;
                 const float pA = tA * wA, pB = tB * wB;
                 if (jz >= 0) acc[jz] += (tA - pA) + (tB - pB);
                 if (jz + 1 < ZC) acc[jz + 1] += pA + pB;

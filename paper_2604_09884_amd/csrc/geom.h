@@ -78,6 +78,7 @@ struct BpCols {
 struct ConeDev {
     int N, V, Nu, Nv;
     double h, du;
+    float inv_du;          // 1 / du
     float dvf, cvf;        // row pitch and (Nv - 1)/2
     const ConeCol *col;    // [V][Nu]
     const ConeView *view;  // [V]
@@ -126,6 +127,7 @@ struct inrct_geom {
         d.Nv = g.n_v;
         d.h = 2.0 / N;
         d.du = g.du;
+        d.inv_du = (float)(1.0 / g.du);
         d.dvf = (float)g.dv;
         d.cvf = 0.5f * (float)(g.n_v - 1);
         d.col = ccols.as<inrct::ConeCol>();
