@@ -154,6 +154,7 @@ def cpu_baseline(p, target_s):
 PROFILE_SOURCES = {
     "mlp": os.path.join("paper_2604_09884_amd", "csrc", "mlp.hip"),
     "cone": os.path.join("paper_2604_09884_amd", "csrc", "cone.hip"),
+    "projector": os.path.join("paper_2604_09884_amd", "csrc", "projector.hip"),
 }
 
 
@@ -429,6 +430,7 @@ def main():
         for k_, rec in util.items():
             figs.setdefault(k_, {}).update(rec)
     e_kernel = ("k_hash_eval" if p.arch.kind == "hash"
+                else "k_eval_grid" if dtype == "fp32"
                 else "k_eval_lds_w<%d>" % (1 if p.arch.kind == "ffn" else 2))
     traffic = _fig(figs, [e_kernel], "traffic_bytes")
     flop_per_point = p.arch.flops_forward()
@@ -461,7 +463,9 @@ def main():
         v_ms = stages["vjp"] / a.steps
         p_bytes = p.n_views * model.n_fov * 4 + m_rays * 4
         pt_bytes = m_rays * 4 + n_grid * 4
-        p_kernels = ["k_cone_fwd_lds<true>", "k_cone_fwd_lds<false>"]
+        # the P stage: the plane-wise transpose, then both tile sets through
+        # the row kernel (figures per step, summed over launches)
+        p_kernels = ["k_transpose2d", "k_cone_fwd_lds<true>"]
         pt_kernels = ["k_cone_prescale", "k_cone_bp_lds<true>"]
         p_traffic = _fig(figs, p_kernels, "traffic_bytes")
         pt_traffic = _fig(figs, pt_kernels, "traffic_bytes")
@@ -476,8 +480,7 @@ def main():
                   "traffic": p_traffic,
                   "hbm_counter_frac": (None if p_traffic is None
                                        else p_traffic / (p_ms * 1e-3) / 8e12),
-                  "valu_busy_counter": _fig(figs, p_kernels[:1], "valu_busy"),
-                  "valu_busy_counter_x": _fig(figs, p_kernels[1:], "valu_busy")},
+                  "valu_busy_counter": _fig(figs, p_kernels[1:], "valu_busy")},
             "PT": {"kernels": pt_kernels, "ms": pt_ms, "bound": "alu",
                    "hbm_alg_bytes": pt_bytes,
                    "hbm_alg_note": "the residual read once, v written once",
@@ -489,7 +492,8 @@ def main():
             "VJP": {"ms": v_ms, "bound": "mfma", "flop": vjp_flop,
                     "achieved_tflops": vjp_flop / (v_ms * 1e-3) / 1e12,
                     "frac": vjp_flop / (v_ms * 1e-3) / PEAK[dtype],
-                    "traffic": _fig(figs, ["k_vjp_w", "k_dw_gemm2"], "traffic_bytes")},
+                    "traffic": _fig(figs, ["k_vjp_w", "k_dw_gemm2", "k_dw_reduce2"],
+                                    "traffic_bytes")},
         }
     out = {
         "metric": ("grad steps/s at 501^3 cone-beam 20 views" if a.config == "c4"

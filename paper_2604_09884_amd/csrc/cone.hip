@@ -360,8 +360,10 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
 }
 
 __device__ __forceinline__ int fx40_int(long long F) { return (int)(F >> 40); }
+// the fraction's upper 32 bits, in units of 2^-32 (fx40_frac's numerator)
+__device__ __forceinline__ float fx40_frac32(long long F) { return (float)(unsigned int)(F >> 8); }
 __device__ __forceinline__ float fx40_frac(long long F) {
-    return (float)(unsigned int)(F >> 8) * 2.3283064365386963e-10f;
+    return fx40_frac32(F) * 2.3283064365386963e-10f;
 }
 
 // Step length h |d| / |d_axis| of ray (column record c, row b), float32,
@@ -543,24 +545,39 @@ __global__ __launch_bounds__(256, 2) void k_cone_fwd_lds(ConeDev g, const ConeTi
         olo = f.olo;
         zlo = f.zlo;
         __syncthreads();
-#pragma unroll
-        for (int sl = 0; sl < kTileS; ++sl) {
+        // Slice sl's taps are read (into buffer sl & 1) while slice sl - 1
+        // is integrated, so the LDS latency overlaps the arithmetic.
+        constexpr int co = YPR ? 1 : kLdsOX, cz = YPR ? kLdsZY : kLdsZX;
+        float v[2][kRows][4], fz[2][kRows], fo[2];
+        auto fetch = [&](int sl, int bf) {
             const int io = fx40_int(Fo);
-            const float fo = fx40_frac(Fo);
+            fo[bf] = fx40_frac(Fo);
             const float *Ls = L + (YPR ? sl * kLdsSY + io : sl + io * kLdsOX);
-            constexpr int co = YPR ? 1 : kLdsOX, cz = YPR ? kLdsZY : kLdsZX;
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
-                const int iz = fx40_int(Fz[r]);
-                const float fz = fx40_frac(Fz[r]);
-                const float *p = Ls + iz * cz;
-                const float v00 = p[0], v01 = p[co], v10 = p[cz], v11 = p[cz + co];
-                const float t0 = fmaf(fo, v01 - v00, v00);
-                const float t1 = fmaf(fo, v11 - v10, v10);
-                acc[r] += fmaf(fz, t1 - t0, t0);
+                const float *p = Ls + fx40_int(Fz[r]) * cz;
+                v[bf][r][0] = p[0];
+                v[bf][r][1] = p[co];
+                v[bf][r][2] = p[cz];
+                v[bf][r][3] = p[cz + co];
+                fz[bf][r] = fx40_frac(Fz[r]);
                 Fz[r] += dFz[r];
             }
             Fo += c.dFo;
+        };
+        fetch(0, 0);
+#pragma unroll
+        for (int sl = 0; sl < kTileS; ++sl) {
+            if (sl + 1 < kTileS) fetch(sl + 1, (sl + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+            const int bf = sl & 1;
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                const float t0 = fmaf(fo[bf], v[bf][r][1] - v[bf][r][0], v[bf][r][0]);
+                const float t1 = fmaf(fo[bf], v[bf][r][3] - v[bf][r][2], v[bf][r][2]);
+                acc[r] += fmaf(fz[bf][r], t1 - t0, t0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     if (t.a0 + lane > a1) return;
@@ -771,25 +788,28 @@ __device__ __forceinline__ void cone_gather_view_w2(const ConeDev &g, const Cone
                 ++b;
                 ph += E1;
             }
-            int ri = (b - blo) * rstride + (a - alo);
+            const float *rp = R + (b - blo) * rstride + (a - alo);
             // band jz = -1 .. ZC - 1: rows with floor(phi) = z0 + jz give
-            // (1 - w) to voxel jz and w to voxel jz + 1
+            // (1 - w) to voxel jz and w to voxel jz + 1.  The weights stay in
+            // units of 2^-32: w is fx40_frac's numerator, 1 - w is 2^32 minus
+            // that (each voxel's terms are summed as products, without
+            // cancellation); the power of two goes into wo_s.
+            const float wo_s = wo * 2.3283064365386963e-10f;
 #pragma unroll
             for (int jz = -1; jz < ZC; ++jz) {
                 // both rows are read unconditionally (R holds the row after
                 // the last), so a band is straight-line code
-                const float rA = R[ri], rB = R[ri + rstride];
-                const float wA = fx40_frac(ph);
-                const float tA = wo * rA;
+                const float rA = rp[0], rB0 = rp[rstride];
                 const long long phB = ph + E1;
                 const bool inB = fx40_int(phB) == z0 + jz;
-                const float wB = fx40_frac(phB);
-                const float tB = inB ? wo * rB : 0.f;
-                const float pA = tA * wA, pB = tB * wB;
-                if (jz >= 0) acc[jz] += (tA - pA) + (tB - pB);
-                if (jz + 1 < ZC) acc[jz + 1] += pA + pB;
+                const float rB = inB ? rB0 : 0.f;
+                const float cA = fx40_frac32(ph), cB = fx40_frac32(phB);
+                const float q = fmaf(cB, rB, cA * rA);
+                const float qn = fmaf(4294967296.f - cB, rB, (4294967296.f - cA) * rA);
+                if (jz >= 0) acc[jz] = fmaf(qn, wo_s, acc[jz]);
+                if (jz + 1 < ZC) acc[jz + 1] = fmaf(q, wo_s, acc[jz + 1]);
                 ph = inB ? phB + E1 : phB;
-                ri += inB ? 2 * rstride : rstride;
+                rp += inB ? 2 * rstride : rstride;
             }
         }
     }
@@ -960,7 +980,8 @@ __global__ __launch_bounds__(256) void k_cone_bp_at(ConeDev g, const float *__re
 }
 
 // ----------------------------------------------------------- host wrappers
-void cone_project(inrct_geom *hd, const float *u, float *z, bool fov_only, hipStream_t s) {
+void cone_project(inrct_geom *hd, const float *u, float *z, bool fov_only, hipStream_t s,
+                  const float *ut) {
     const ConeDev d = hd->cone();
     const ConeTile *t = hd->tiles.as<ConeTile>();
     if (hd->n_tile_y > 0) {
@@ -969,8 +990,14 @@ void cone_project(inrct_geom *hd, const float *u, float *z, bool fov_only, hipSt
         INRCT_CHECK_LAUNCH();
     }
     if (hd->n_tile_x > 0) {
-        hipLaunchKernelGGL(k_cone_fwd_lds<false>, dim3((unsigned)hd->n_tile_x), dim3(256), 0, s,
-                           d, t + hd->n_tile_y, hd->n_tile_x, u, z, fov_only ? 1 : 0);
+        // with ut ([z][x][y]) an x-principal ray's slices are rows, as a
+        // y-principal ray's are in u: the same kernel and footprints apply
+        if (ut)
+            hipLaunchKernelGGL(k_cone_fwd_lds<true>, dim3((unsigned)hd->n_tile_x), dim3(256), 0,
+                               s, d, t + hd->n_tile_y, hd->n_tile_x, ut, z, fov_only ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_cone_fwd_lds<false>, dim3((unsigned)hd->n_tile_x), dim3(256), 0,
+                               s, d, t + hd->n_tile_y, hd->n_tile_x, u, z, fov_only ? 1 : 0);
         INRCT_CHECK_LAUNCH();
     }
     if (hd->n_tile_f > 0) {

@@ -144,10 +144,21 @@ void cone_build(inrct_geom *h, Arena &a);
 void check_geom_args(const ct_geometry *g, const inr_grid *grid);
 inrct_geom *fresh_geom(const ct_geometry *g, const inr_grid *grid);
 void build_geom(inrct_geom *h, Arena &ar);
-void cone_project(inrct_geom *h, const float *u, float *z, bool fov_only, hipStream_t s);
+void cone_project(inrct_geom *h, const float *u, float *z, bool fov_only, hipStream_t s,
+                  const float *ut = nullptr);
 // z = P u; with fov_only the caller guarantees u = 0 outside the FOV (the
 // projector may then skip slices that lie outside it).
-void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov_only = false);
+// z = P u.  For a cone geometry, ut (optional) is u transposed in every xy
+// plane ([z][x][y]); given it, x-principal rays read it with the y-principal
+// kernel (rows along their own axis) instead of staging columns of u.
+void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov_only = false,
+             const float *ut = nullptr);
+// ut = u transposed in each of `planes` N x N planes
+void transpose_planes(const float *u, float *ut, int N, int planes, hipStream_t s);
+// a cone geometry whose projector has x-principal tiles (those read ut)
+inline bool geom_reads_transpose(const inrct_geom *g) {
+    return g->g.kind == INRCT_CONE3D && g->n_tile_x > 0;
+}
 void cone_backproject(inrct_geom *h, const float *r, float *v, hipStream_t s);
 void cone_backproject_at(inrct_geom *h, const float *r, const int32_t *idx, int64_t k,
                          float *out, hipStream_t s);

@@ -132,12 +132,15 @@ __device__ __forceinline__ void slice_range(long long F0, long long dF, int N,
 }
 
 // ----------------------------------------------------------- forward, 2D
-// ut = u transposed ([x][y]), so that x-principal rays read rows too.
+// ut = u transposed in every xy plane ([z][x][y]; blockIdx.z is the plane),
+// so that x-principal rays read rows too.
 __global__ __launch_bounds__(256) void k_transpose2d(const float *__restrict__ u,
                                                      float *__restrict__ ut, int N) {
     __shared__ float t[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    u += (size_t)blockIdx.z * N * N;
+    ut += (size_t)blockIdx.z * N * N;
     for (int k = 0; k < 32; k += 8) {
         const int x = x0 + tx, y = y0 + ty + k;
         if (x < N && y < N) t[ty + k][tx] = u[(size_t)y * N + x];
@@ -388,7 +391,14 @@ int64_t geom_rays(const inrct_geom *g) { return g->m(); }
 int geom_dim(const inrct_geom *g) { return g->dim; }
 int geom_N(const inrct_geom *g) { return g->N; }
 
-void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov_only) {
+void transpose_planes(const float *u, float *ut, int N, int planes, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose2d, dim3((unsigned)cdiv(N, 32), (unsigned)cdiv(N, 32), planes),
+                       dim3(256), 0, s, u, ut, N);
+    INRCT_CHECK_LAUNCH();
+}
+
+void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov_only,
+             const float *ut) {
     const GeomDev d = geom->dev();
     if (d.kind == INRCT_PAR2D || d.kind == INRCT_FAN2D) {
         float *ut = geom->ut.as<float>();
@@ -399,7 +409,7 @@ void project(inrct_geom *geom, const float *u, float *z, hipStream_t s, bool fov
                            0, s, d, u, ut, z);
         INRCT_CHECK_LAUNCH();
     } else {
-        cone_project(geom, u, z, fov_only, s);
+        cone_project(geom, u, z, fov_only, s, ut);
     }
 }
 

@@ -280,6 +280,7 @@ struct inr_ctx {
     const float *B = nullptr, *y = nullptr;
     int64_t m_cap = 0;  // rays the r buffer holds
     DevBuf u, r, v, g, idx;
+    DevBuf ut;  // cone beam: u transposed in every xy plane ([z][x][y])
     // optional stage timing: events[slot][stage][0=start, 1=end]
     std::vector<hipEvent_t> events;
     int t_slots = 0, t_used = 0;
@@ -295,13 +296,18 @@ struct inr_ctx {
 
 namespace inrct {
 // The context's own buffers: u and v on the grid (v only at I when v_mode
-// is INRCT_V_AT_I), r on the rays, g, and I.  u outside the FOV is 0 and no
-// step writes there, so it is cleared once here.
+// is INRCT_V_AT_I), r on the rays, g, and I; for a cone geometry also the
+// plane-wise transpose of u that the x-principal rays read.  u outside the
+// FOV is 0 and no step writes there, so it is cleared once here.
 static void build_ctx(inr_ctx *c, long long n_grid, long long m_rays, long long n_params,
-                      Arena &ar) {
+                      bool cone, Arena &ar) {
     c->m_cap = m_rays;
     c->u.alloc(ar, sizeof(float) * n_grid);
     zero_fill(ar, c->u);
+    if (cone) {
+        c->ut.alloc(ar, sizeof(float) * n_grid);
+        zero_fill(ar, c->ut);
+    }
     c->r.alloc(ar, sizeof(float) * m_rays);
     c->v.alloc(ar, sizeof(float) * (c->cfg.v_mode == INRCT_V_FULL ? n_grid : c->cfg.k));
     c->g.alloc(ar, sizeof(float) * n_params);
@@ -378,6 +384,7 @@ int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *c
             return c;
         };
         const long long ng = model->n_grid, mr = geom_rays(geom), np = model->n_params;
+        const bool cone = geom->g.kind == INRCT_CONE3D;
         inr_ctx *c = fresh();
         try {
             c->model = model;
@@ -388,7 +395,7 @@ int inr_ctx_create(inrct_model *model, inrct_geom *geom, const inrct_step_cfg *c
             c->B = B;
             c->y = y;
             build_in_workspace(c, c->ws, ws, ws_bytes, stream, fresh,
-                               [&](inr_ctx *x, Arena &ar) { build_ctx(x, ng, mr, np, ar); });
+                               [&](inr_ctx *x, Arena &ar) { build_ctx(x, ng, mr, np, cone, ar); });
         } catch (...) {
             delete c;
             throw;
@@ -432,7 +439,9 @@ int64_t inrct_workspace_bytes(int which, const inr_arch *arch, const ct_geometry
                     c->cfg = *cfg;
                     return c;
                 },
-                [&](inr_ctx *x, Arena &ar) { build_ctx(x, ng, mr, np, ar); });
+                [&](inr_ctx *x, Arena &ar) {
+                    build_ctx(x, ng, mr, np, g->kind == INRCT_CONE3D, ar);
+                });
         } else {
             set_error("unknown workspace kind %d", which);
             throw Error{INRCT_EINVAL};
@@ -512,7 +521,10 @@ static void grad_step(inr_ctx *c, uint64_t step, inrct_geom *geom, const float *
     model_eval_fov(m, c->theta, c->B, u, s);
     mark(0, 1);
     mark(1, 0);
-    project(geom, u, r, s, true);  // u vanishes outside the FOV
+    // the plane-wise transpose of u only when this geometry's projector reads it
+    float *ut = c->ut.ptr && geom_reads_transpose(geom) ? c->ut.as<float>() : nullptr;
+    if (ut) transpose_planes(u, ut, m->N, m->N, s);
+    project(geom, u, r, s, true, ut);  // u vanishes outside the FOV
     mark(1, 1);
     // step 2: r = dL/dz, v = P^T r
     mark(2, 0);

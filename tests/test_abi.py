@@ -131,10 +131,11 @@ def test_workspace_bytes_on_the_host():
     wc = lib.inrct_workspace_bytes(L.INRCT_WS_CTX, ref(a), ref(g), ref(grid), 300, ref(cfg))
     assert wg > 0 and wm > 0 and wc > 0
     assert wm == lib.inrct_workspace_bytes(L.INRCT_WS_MODEL, ref(a), None, ref(grid), 300, None)
-    # the context holds u, r, v on the grid or rays, g and I (each 256-byte aligned)
+    # the context holds u, its plane-wise transpose (cone beam), r, v on the
+    # grid or rays, g and I (each 256-byte aligned)
     n_grid, m = 32 ** 3, 4 * 48 * 48
-    lo = 4 * (2 * n_grid + m + 394753) + 4 * 300
-    assert lo <= wc <= lo + 5 * 256
+    lo = 4 * (3 * n_grid + m + 394753) + 4 * 300
+    assert lo <= wc <= lo + 6 * 256
     # v only at I is smaller
     cfg_i = L.StepCfg(L.INRCT_LS, 300, 0, 1e-3, 0.9, 0.999, 1e-8, L.INRCT_V_AT_I)
     assert lib.inrct_workspace_bytes(L.INRCT_WS_CTX, ref(a), ref(g), ref(grid), 300,
