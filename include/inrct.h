@@ -184,6 +184,19 @@ int inrct_geom_destroy(inrct_geom *geom);
 /* number of rays m = n_views * n_v * n_u */
 int64_t inrct_geom_n_rays(const inrct_geom *geom);
 
+/* Which adjoint formulation ct_backproject uses for this geometry (chosen
+ * when the geometry is built; every form computes the same v = P^T r up to
+ * FP32 summation order): INRCT_ADJ_2D (parallel or fan beam),
+ * INRCT_ADJ_DIRECT (cone, gathers from global memory), INRCT_ADJ_WALK (cone,
+ * detector footprints staged in LDS, row walk per voxel column),
+ * INRCT_ADJ_WALK2 (the same, rows half a voxel to a voxel apart: two rows
+ * per voxel band, no branch).  -1 for a null handle. */
+#define INRCT_ADJ_2D 0
+#define INRCT_ADJ_DIRECT 1
+#define INRCT_ADJ_WALK 2
+#define INRCT_ADJ_WALK2 3
+int inrct_geom_adjoint_kind(const inrct_geom *geom);
+
 /* z = P u.  u: device [grid], z: device [rays].  The whole grid is
  * integrated (values outside the FOV count). */
 int ct_project(inrct_geom *geom, const float *u, float *z, hipStream_t stream);

@@ -742,6 +742,68 @@ __device__ __forceinline__ void cone_gather_view(const ConeDev &g, const ConeVie
 // (used only when it lies in the band), with no data-dependent branch.  R
 // must hold every row whose stencil reaches the segment, zeros for rows off
 // the detector, and one more row (the walk reads a row past the last).
+// One column's contribution to voxels (o, s, z0 .. z0 + ZC - 1) under the
+// walk below: acc[jz] += wo_s 2^32 (sum over its rows of the row's z weight
+// for voxel z0 + jz times the residual), for a column record c at slice s,
+// with rows read from R (row stride rstride, this column's entries starting
+// at R + (b - blo) rstride).  Rows must lie between half a voxel and one
+// voxel apart along z (E1 in [1/2, 1)): every voxel band [z, z + 1) then
+// holds one or two rows, so the walk visits, for each band, the band's first
+// row and the row after it (used only when it lies in the band), with no
+// data-dependent branch.  R must hold every row whose stencil reaches the
+// segment, zeros for rows off the detector, and one more row (the walk
+// reads a row past the last).
+template <int ZC>
+__device__ __forceinline__ void w2_column(const float *__restrict__ R, int rstride,
+                                          const ConeCol &c, int s, int a_local, int blo, int z0,
+                                          float wo_s, float (&acc)[ZC]) {
+    const long long E0 = c.Z0 + (long long)s * c.D0;
+    const long long E1 = c.Z1 + (long long)s * c.D1;
+    // the first row whose stencil reaches z0 - 1: an estimate from the high
+    // bits (E1 >= 2^39, so E1 >> 24 keeps 16 bits and the estimate is within
+    // a tenth of a row), then exact
+    const long long lo_t = (long long)(z0 - 1) * (1LL << 40);
+    int b = (int)floorf((float)(int)((lo_t - E0) >> 24) *
+                        __builtin_amdgcn_rcpf((float)(int)(E1 >> 24)));
+    long long ph = E0 + (long long)b * E1;
+    if (ph >= lo_t) {
+        --b;
+        ph -= E1;
+    }
+    if (ph < lo_t) {
+        ++b;
+        ph += E1;
+    }
+    if (ph < lo_t) {
+        ++b;
+        ph += E1;
+    }
+    const float *rp = R + (b - blo) * rstride + a_local;
+    // band jz = -1 .. ZC - 1: rows with floor(phi) = z0 + jz give (1 - w) to
+    // voxel jz and w to voxel jz + 1.  The weights stay in units of 2^-32: w
+    // is fx40_frac's numerator, 1 - w is 2^32 minus that (each voxel's terms
+    // are summed as products, without cancellation); the power of two is in
+    // wo_s.
+#pragma unroll
+    for (int jz = -1; jz < ZC; ++jz) {
+        // both rows are read unconditionally (R holds the row after the
+        // last), so a band is straight-line code
+        const float rA = rp[0], rB0 = rp[rstride];
+        const long long phB = ph + E1;
+        const bool inB = fx40_int(phB) == z0 + jz;
+        const float rB = inB ? rB0 : 0.f;
+        const float cA = fx40_frac32(ph), cB = fx40_frac32(phB);
+        const float q = fmaf(cB, rB, cA * rA);
+        const float qn = fmaf(4294967296.f - cB, rB, (4294967296.f - cA) * rA);
+        if (jz >= 0) acc[jz] = fmaf(qn, wo_s, acc[jz]);
+        if (jz + 1 < ZC) acc[jz + 1] = fmaf(q, wo_s, acc[jz + 1]);
+        ph = inB ? phB + E1 : phB;
+        rp += inB ? 2 * rstride : rstride;
+    }
+}
+
+// cone_gather_view for geometries whose detector rows are between half a
+// voxel and one voxel apart along z at every column and slice (w2_column).
 template <int ZC>
 __device__ __forceinline__ void cone_gather_view_w2(const ConeDev &g, const ConeView &vg,
                                                     const float *__restrict__ R, int rstride,
@@ -767,50 +829,7 @@ __device__ __forceinline__ void cone_gather_view_w2(const ConeDev &g, const Cone
             if (io != o && io != o - 1) continue;
             const float fo = fx40_frac(Fo);
             const float wo = io == o ? 1.f - fo : fo;
-            const long long E0 = c.Z0 + (long long)s * c.D0;
-            const long long E1 = c.Z1 + (long long)s * c.D1;
-            // the first row whose stencil reaches z0 - 1: an estimate from
-            // the high bits (E1 >= 2^39, so E1 >> 24 keeps 16 bits and the
-            // estimate is within a tenth of a row), then exact
-            const long long lo_t = (long long)(z0 - 1) * (1LL << 40);
-            int b = (int)floorf((float)(int)((lo_t - E0) >> 24) *
-                                __builtin_amdgcn_rcpf((float)(int)(E1 >> 24)));
-            long long ph = E0 + (long long)b * E1;
-            if (ph >= lo_t) {
-                --b;
-                ph -= E1;
-            }
-            if (ph < lo_t) {
-                ++b;
-                ph += E1;
-            }
-            if (ph < lo_t) {
-                ++b;
-                ph += E1;
-            }
-            const float *rp = R + (b - blo) * rstride + (a - alo);
-            // band jz = -1 .. ZC - 1: rows with floor(phi) = z0 + jz give
-            // (1 - w) to voxel jz and w to voxel jz + 1.  The weights stay in
-            // units of 2^-32: w is fx40_frac's numerator, 1 - w is 2^32 minus
-            // that (each voxel's terms are summed as products, without
-            // cancellation); the power of two goes into wo_s.
-            const float wo_s = wo * 2.3283064365386963e-10f;
-#pragma unroll
-            for (int jz = -1; jz < ZC; ++jz) {
-                // both rows are read unconditionally (R holds the row after
-                // the last), so a band is straight-line code
-                const float rA = rp[0], rB0 = rp[rstride];
-                const long long phB = ph + E1;
-                const bool inB = fx40_int(phB) == z0 + jz;
-                const float rB = inB ? rB0 : 0.f;
-                const float cA = fx40_frac32(ph), cB = fx40_frac32(phB);
-                const float q = fmaf(cB, rB, cA * rA);
-                const float qn = fmaf(4294967296.f - cB, rB, (4294967296.f - cA) * rA);
-                if (jz >= 0) acc[jz] = fmaf(qn, wo_s, acc[jz]);
-                if (jz + 1 < ZC) acc[jz + 1] = fmaf(q, wo_s, acc[jz + 1]);
-                ph = inB ? phB + E1 : phB;
-                rp += inB ? 2 * rstride : rstride;
-            }
+            w2_column<ZC>(R, rstride, c, s, a - alo, blo, z0, wo * 2.3283064365386963e-10f, acc);
         }
     }
 }

@@ -569,6 +569,13 @@ int inrct_geom_destroy(inrct_geom *geom) {
 
 int64_t inrct_geom_n_rays(const inrct_geom *geom) { return geom ? geom->m() : -1; }
 
+int inrct_geom_adjoint_kind(const inrct_geom *geom) {
+    if (!geom) return -1;
+    if (geom->g.kind != INRCT_CONE3D) return INRCT_ADJ_2D;
+    if (!geom->bp_lds) return INRCT_ADJ_DIRECT;
+    return geom->bp_w2 ? INRCT_ADJ_WALK2 : INRCT_ADJ_WALK;
+}
+
 int ct_project(inrct_geom *geom, const float *u, float *z, hipStream_t stream) {
     return guarded([&] {
         INRCT_REQUIRE(geom && u && z, "null argument");

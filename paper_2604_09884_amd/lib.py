@@ -17,6 +17,7 @@ INRCT_FP32, INRCT_BF16 = 0, 1
 INRCT_LS, INRCT_FLS = 0, 1
 INRCT_V_FULL, INRCT_V_AT_I = 0, 1
 INRCT_WS_GEOM, INRCT_WS_MODEL, INRCT_WS_CTX = 1, 2, 3
+INRCT_ADJ_2D, INRCT_ADJ_DIRECT, INRCT_ADJ_WALK, INRCT_ADJ_WALK2 = 0, 1, 2, 3
 
 c_void_p = ctypes.c_void_p
 c_int = ctypes.c_int
@@ -82,6 +83,7 @@ def load():
             ctypes.POINTER(P)])
     _proto(lib, "inrct_geom_destroy", c_int, [P])
     _proto(lib, "inrct_geom_n_rays", c_i64, [P])
+    _proto(lib, "inrct_geom_adjoint_kind", c_int, [P])
     _proto(lib, "ct_project", c_int, [P, P, P, P])
     _proto(lib, "ct_backproject", c_int, [P, P, P, P])
     _proto(lib, "ct_backproject_at", c_int, [P, P, P, c_i64, P, P])
@@ -121,7 +123,7 @@ def check(status):
 
 
 EXPORTED = [
-    "inrct_last_error", "inrct_workspace_bytes", "inrct_geom_create", "inrct_geom_destroy", "inrct_geom_n_rays",
+    "inrct_last_error", "inrct_workspace_bytes", "inrct_geom_create", "inrct_geom_destroy", "inrct_geom_n_rays", "inrct_geom_adjoint_kind",
     "ct_project", "ct_backproject", "ct_backproject_at", "inrct_residual_loss",
     "inrct_model_create", "inrct_model_destroy", "inrct_model_n_params",
     "inrct_model_n_fov", "inr_eval_grid", "inr_eval_points", "inr_vjp_subsampled",

@@ -125,6 +125,7 @@ class Geometry:
                                       self.ws_bytes, _stream(), ctypes.byref(h)))
         self.handle = h
         self.n_rays = lib.inrct_geom_n_rays(h)
+        self.adjoint_kind = lib.inrct_geom_adjoint_kind(h)  # INRCT_ADJ_*
         self.grid_shape = (problem.N,) * problem.dim
         self.proj_shape = ((len(self.angles), problem.n_u) if problem.dim == 2 else
                            (len(self.angles), problem.n_v, problem.n_u))

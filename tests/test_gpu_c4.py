@@ -94,7 +94,9 @@ def _window_adjoint(vox, r3, N):
 
 
 def test_c4_backprojection_sampled_voxels(geom):
-    from paper_2604_09884_amd import ops
+    from paper_2604_09884_amd import lib as L, ops
+    # the benchmark geometry takes the branch-free walk
+    assert geom.adjoint_kind == L.INRCT_ADJ_WALK2
     N = P4.N
     r = RNG(12).standard_normal(geom.n_rays).astype(np.float32)
     v = host(ops.ct_backproject(geom, dev(r))).ravel()

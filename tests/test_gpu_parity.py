@@ -33,6 +33,9 @@ def _problems():
         # detector rows 0.68 voxel apart along z: the adjoint's branch-free
         # two-rows-per-voxel walk
         ("cone-w2", configs.cone_problem(40, 5, 60)),
+        # the same walk with 2.5 detector columns per voxel and axis-aligned
+        # views (about four columns cover each voxel)
+        ("cone-walk2", configs.cone_problem(32, 4, 83).with_(n_v=44, dv=3.1 / 44)),
         # views at 45 degree multiples: tiles whose columns change principal
         # axis take the direct-gather route
         ("cone-45deg", configs.cone_problem(26, 8, 36).with_(n_v=20, dv=3.1 / 20)),
@@ -48,11 +51,25 @@ def _problems():
     ]
 
 
+def test_cone_cases_cover_every_adjoint_kind():
+    from paper_2604_09884_amd import lib as L
+    ops = _ops()
+    kinds = {}
+    for name, p in _problems():
+        if p.dim == 3:
+            g = ops.Geometry(p)
+            kinds[name] = g.adjoint_kind
+            g.close()
+    say("adjoint kinds", kinds)
+    assert {L.INRCT_ADJ_DIRECT, L.INRCT_ADJ_WALK, L.INRCT_ADJ_WALK2} <= set(kinds.values())
+
+
 @pytest.mark.parametrize("name,p", _problems(), ids=[n for n, _ in _problems()])
 def test_project_and_backproject_match_oracle(name, p):
     ops = _ops()
     say("case", name)
     g = ops.Geometry(p)
+    say(name, "adjoint kind", g.adjoint_kind)
     P = joseph.problem_matrix(p)
     u = RNG(1).standard_normal(p.n_grid)
     r = RNG(2).standard_normal(P.shape[0])
