@@ -1527,8 +1527,12 @@ __global__ void k_dw_reduce(const GemmTile *__restrict__ tiles, const float *__r
 // slice of points, so every delta and activation row of the slice is read
 // once per column block (layers of width 256 have one block).  The tile that
 // starts at column 0 also sums the delta rows (the bias gradient).  Four
-// waves, each a 128 x 128 quadrant (4 x 4 MFMA tiles); operands come straight
-// from global memory, two k-steps per group, double-buffered.
+// waves, each a 128 x 128 quadrant (4 x 4 MFMA tiles).  The slice streams in
+// groups of 32 points: a group is 16 delta and 16 activation fragments of
+// 1 KB (256 rows x 16 points), copied straight from global memory into a
+// ring of four 32 KB LDS slots, three groups in flight (each wave copies
+// eight fragments and waits on its own copy counter; a barrier publishes the
+// group), so every row is read from memory once per workgroup.
 struct GemmTile2 {
     long long dlt_off;    // element offset of delta_l rows
     long long act_off;    // element offset of a_{l-1} rows
@@ -1536,31 +1540,24 @@ struct GemmTile2 {
     int M, R, tn, bias;   // rows, inputs, first column, sums the bias gradient
 };
 constexpr int kDwPart = 256 * 256 + 256;  // partial floats per (tile, slice)
+constexpr int kDwSlot = 32 * 1024;        // one group: 32 fragments of 1 KB
 
 __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ tiles,
                                                   const __bf16 *__restrict__ dlt,
                                                   const __bf16 *__restrict__ act, long long P,
                                                   long long ncols, int kslice, int accumulate,
                                                   float *__restrict__ part, int ntiles) {
+    __shared__ __attribute__((aligned(16))) char ring[4 * kDwSlot];
     const GemmTile2 T = tiles[blockIdx.x];
     const int ks = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int h = lane >> 5, i = lane & 31;
     const int wm = wave >> 1, wn = wave & 1;
     const long long p0 = (long long)ks * kslice;
     long long p1 = p0 + kslice;
     if (p1 > ncols) p1 = ncols;
-    const __bf16 *ap[4], *bp[4];
-    bool aok[4], bok[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int row = wm * 128 + 32 * a + i;
-        aok[a] = row < T.M;
-        ap[a] = dlt + T.dlt_off + (long long)(aok[a] ? row : 0) * P + 8 * h;
-        const int col = T.tn + wn * 128 + 32 * a + i;
-        bok[a] = col < T.R;
-        bp[a] = act + T.act_off + (long long)(bok[a] ? col : 0) * P + 8 * h;
-    }
+    const int G = p1 > p0 ? (int)((p1 - p0) / 32) : 0;
     f32x16 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -1568,57 +1565,77 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
         for (int b = 0; b < 4; ++b) acc[a][b] = (f32x16){0};
     float bs[4] = {0.f, 0.f, 0.f, 0.f};
     const bool dob = T.bias && wn == 0;
-    bf16x8 zero;
+    if (G > 0) {
+        // fragment f of a group (lane l: row 32 (f / 2 % 8) + l % 32, points
+        // 16 (f % 2) + 8 (l / 32) .. + 7): f < 16 delta rows, f >= 16
+        // activation rows of this tile's columns.  Rows past the layer read
+        // its last row (their products are never summed into a gradient).
+        const __bf16 *src[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) zero[q] = (__bf16)0.f;
-    bf16x8 A[2][4][2], B[2][4][2];
-    // Rows and columns outside the layer read row 0 (always valid) and are
-    // zeroed after the load: no branch around a load, so the wait before a
-    // group's products counts only that group's loads.
-    auto load = [&](int buf, long long p) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                A[buf][a][j] = *(const bf16x8 *)(ap[a] + p + 16 * j);
-                B[buf][a][j] = *(const bf16x8 *)(bp[a] + p + 16 * j);
-            }
-    };
-    auto mask = [&](int buf) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                if (!aok[a]) A[buf][a][j] = zero;
-                if (!bok[a]) B[buf][a][j] = zero;
-            }
-    };
-    auto compute = [&](int buf) {
-        mask(buf);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[buf][a][j], B[buf][b][j],
-                                                                        acc[a][b], 0, 0, 0);
-        if (dob) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) bs[a] += (float)A[buf][a][j][q];
+        for (int q = 0; q < 8; ++q) {
+            const int f = 8 * wave + q;
+            const int row = 32 * ((f >> 1) & 7) + i, off = 16 * (f & 1) + 8 * h;
+            if (f < 16) src[q] = dlt + T.dlt_off + (long long)min(row, T.M - 1) * P + p0 + off;
+            else src[q] = act + T.act_off + (long long)min(T.tn + row, T.R - 1) * P + p0 + off;
         }
-    };
-    // the slice length is a multiple of 128 points: groups of 32 come in pairs
-    if (p0 < p1) load(0, p0);
-    for (long long p = p0; p < p1; p += 64) {
-        load(1, p + 32);
-        compute(0);
-        if (p + 64 < p1) load(0, p + 64);
-        compute(1);
+        const unsigned lds0 = __builtin_amdgcn_readfirstlane(
+            (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring);
+        // copies of group g (clamped to the last, so that every wave issues
+        // the same number of copies per group whatever G is)
+        auto issue = [&](int g, int slot) {
+            const long long dp = 32LL * (g < G ? g : G - 1);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :
+                             : "s"(lds0 + (unsigned)(slot * kDwSlot + (8 * wave + q) * 1024)),
+                               "v"(src[q] + dp)
+                             : "memory", "m0");
+        };
+        issue(0, 0);
+        issue(1, 1);
+        issue(2, 2);
+        for (int g = 0; g < G; ++g) {
+            // this wave's copies of group g have landed (those of g + 1 and
+            // g + 2 may be in flight); the barrier publishes every wave's
+            asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+            __syncthreads();
+            // the slot read through an address the compiler cannot trace, so
+            // no read is hoisted above the wait and barrier
+            unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring +
+                           (unsigned)((g & 3) * kDwSlot) + lane * 16;
+            asm volatile("" : "+v"(off));
+            const bf16x8 *F = (const bf16x8 *)(__attribute__((address_space(3))) const bf16x8 *)(size_t)off;
+            bf16x8 A[2][4], B[2][4];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    A[j][a] = F[(((wm * 4 + a) << 1) | j) * 64];
+                    B[j][a] = F[(16 + (((wn * 4 + a) << 1) | j)) * 64];
+                }
+            // the slot of group g - 1 is free (every wave passed this
+            // barrier): group g + 3 goes there
+            issue(g + 3, (g + 3) & 3);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[j][a], B[j][b],
+                                                                            acc[a][b], 0, 0, 0);
+            if (dob) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) bs[a] += (float)A[j][a][q];
+            }
+        }
+        // the copies of the groups never consumed land before the wave ends
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     float *__restrict__ out = part + ((long long)ks * ntiles + blockIdx.x) * kDwPart;
 #pragma unroll
