@@ -468,11 +468,13 @@ __device__ __forceinline__ void stage_footprint(float *__restrict__ L, const flo
             }
         }
     } else {
-        // rows (o, z): lane = (z offset, s), eight z rows of eight slices
-        const int sl = lane & 7, zq = lane >> 3;
+        // rows (o, z): lane = (z offset, s), kZq z rows of kTileS slices per
+        // copy; lanes past the footprint's z extent copy nothing
+        constexpr int kZq = 64 / kTileS;
+        const int sl = lane % kTileS, zq = lane / kTileS;
         if (inside) {
             const long long loff = zq * NN + sl;
-            for (int zb = 0; zb < f.zext; zb += 8) {
+            for (int zb = 0; zb < f.zext; zb += kZq) {
                 if (zb + zq >= f.zext) break;  // (this lane's z rows are done)
                 const float *row = u + (((long long)(f.zlo + zb) * N + f.olo + w) * N + s0) + loff;
                 for (int o = w; o < f.oext; o += 4, row += 4 * N)
@@ -484,9 +486,10 @@ __device__ __forceinline__ void stage_footprint(float *__restrict__ L, const flo
         for (int o = w; o < f.oext; o += 4) {
             const int og = f.olo + o;
             const bool oin = og >= 0 && og < N && sg < N;
-            for (int zb = 0; zb < f.zext; zb += 8) {
+            for (int zb = 0; zb < f.zext; zb += kZq) {
+                if (zb + zq >= f.zext) break;
                 const int zg = f.zlo + zb + zq;
-                const float *src = oin && zb + zq < f.zext && zg >= 0 && zg < N
+                const float *src = oin && zg >= 0 && zg < N
                                        ? u + (zg * NN + (long long)og * N + sg)
                                        : zeros + lane;
                 __builtin_amdgcn_global_load_lds(src, L + o * kLdsOX + zb * kLdsZX, 4, 0, 0);

@@ -57,7 +57,7 @@ struct ConeView {
 // every slice where some ray passes the FOV cylinder (all a projection of
 // an image that vanishes outside the FOV needs).  An empty range has
 // lo > hi.
-constexpr int kTileA = 64, kTileB = 24, kTileS = 8;
+constexpr int kTileA = 64, kTileB = 24, kTileS = 4;
 struct ConeTile {
     int j, a0, b0;
     int slo, shi, flo, fhi;
