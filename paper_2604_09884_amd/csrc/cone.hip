@@ -9,7 +9,7 @@
 // exactly the interpolation weights P applies, and neither does float64
 // work per sample.
 //
-// P: a workgroup integrates a tile of 64 x 32 rays of one view, slice chunk
+// P: a workgroup integrates a tile of 64 x 24 rays of one view, slice chunk
 // by slice chunk, from the chunk's footprint of u staged in LDS.
 // P^T: one thread per (x, y) voxel column segment of kZc voxels; view by
 // view the block's detector footprint is staged in LDS; the detector
@@ -424,8 +424,8 @@ __device__ __forceinline__ void range40_exact(long long F0, long long dF, int N,
 // in-plane position and its weight).  Slices are visited in chunks of kTileS: the
 // chunk's footprint of u (every tap of every ray of the tile, zero outside
 // the grid) is staged in LDS with coalesced loads, then every sample reads
-// its four taps from LDS.  Two workgroups share a CU, so one stages while
-// the other integrates.
+// its four taps from LDS.  A chunk's footprint is small enough (31 KB) for
+// four workgroups to share a CU, so some stage while the others integrate.
 // Stages the footprint with direct global -> LDS copies (each lane's dword
 // lands at the wave's uniform LDS address + 4 lane); lanes whose tap lies
 // outside the grid copy a zero.  Consecutive lanes copy consecutive LDS
@@ -501,7 +501,7 @@ __device__ __forceinline__ void stage_footprint(float *__restrict__ L, const flo
 constexpr int kRows = kTileB / 4;  // rays per thread (one column)
 
 template <bool YPR>
-__global__ __launch_bounds__(256, 2) void k_cone_fwd_lds(ConeDev g, const ConeTile *__restrict__ tiles,
+__global__ __launch_bounds__(256, 4) void k_cone_fwd_lds(ConeDev g, const ConeTile *__restrict__ tiles,
                                                          int ntiles, const float *__restrict__ u,
                                                          float *__restrict__ zout, int fov_only) {
     __shared__ float L[YPR ? kLdsFloatsY : kLdsFloatsX];
