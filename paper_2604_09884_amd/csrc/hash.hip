@@ -12,10 +12,9 @@
 // dW then comes from fixed-order sums over slices of points and a
 // fixed-order sum of the slices.  The tables' gradient is a sum over (point,
 // level, cell vertex) contributions: they are sorted by table entry with a
-// stable radix sort (equal entries keep the points' order) and each entry's
-// run is summed in order.  No atomics: results are bitwise repeatable.
-#include <hipcub/hipcub.hpp>
-
+// stable LSD radix sort (equal entries keep the points' order; below) and
+// each entry's run is summed in order.  No atomics: results are bitwise
+// repeatable.
 #include "model.h"
 
 namespace inrct {
@@ -285,10 +284,155 @@ __global__ __launch_bounds__(256) void k_hash_zero(float *__restrict__ p, long l
     if (i < n) p[i] = 0.f;
 }
 
+// ------------------------------------------------ stable LSD radix sort
+// Sorts (key, position) pairs by the low `bits` bits of the key, eight bits
+// per pass; the last pass moves the contribution values themselves (gathered
+// through the positions), so the run sums below read them contiguously.
+// Items are taken in tiles of kRsTile in index order; within a tile, item
+// it * 256 + thread comes before item (it + 1) * 256 + thread, and within a
+// round of 256 the wave and lane order is the index order.  An item's place
+// is its digit's start in the output, plus the items of that digit in earlier
+// tiles, earlier rounds, earlier waves of its round and lower lanes of its
+// wave (found with ballots), so equal keys keep their input order.  Counts
+// are per wave and per digit in LDS: no atomics.
+constexpr int kRsItems = 8, kRsTile = 256 * kRsItems, kRsDigits = 256;
+
+// lanes of this wave (among `live`) whose digit equals this lane's
+__device__ __forceinline__ uint64_t rs_peers(unsigned dg, uint64_t live) {
+    uint64_t m = live;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t on = __ballot((dg >> b) & 1u);
+        m &= ((dg >> b) & 1u) ? on : ~on;
+    }
+    return m;
+}
+
+// number of lanes below this one set in m
+__device__ __forceinline__ int rs_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// inclusive scan over the 256 threads of the block; *total = the block's sum
+__device__ __forceinline__ uint32_t rs_block_scan(uint32_t x, uint32_t *sw, uint32_t *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) sw[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t v = sw[q];
+        off += q < w ? v : 0u;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return x + off;
+}
+
+// per tile and digit: the number of items (cnt[digit * ntiles + tile])
+__global__ __launch_bounds__(256) void k_rs_count(const uint32_t *__restrict__ key, long long n,
+                                                  int sh, int ntiles, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t wc[4][kRsDigits];
+    const int tid = threadIdx.x, w = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][tid] = 0u;
+    const long long base = (long long)blockIdx.x * kRsTile;
+    uint32_t kk[kRsItems];
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const long long i = base + it * 256 + tid;
+        kk[it] = i < n ? key[i] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const bool ok = base + it * 256 + tid < n;
+        const unsigned dg = (kk[it] >> sh) & 255u;
+        const uint64_t pm = rs_peers(dg, __ballot(ok));
+        // one lane per digit group (its lowest) adds the group's size; the
+        // wave's LDS accesses are carried out in order
+        if (ok && rs_below(pm) == 0) wc[w][dg] += (uint32_t)__popcll(pm);
+    }
+    __syncthreads();
+    cnt[(size_t)tid * ntiles + blockIdx.x] = wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+}
+
+// one block per digit: exclusive prefix of the digit's tile counts, in place;
+// tot[digit] = the digit's total
+__global__ __launch_bounds__(256) void k_rs_scan(uint32_t *__restrict__ cnt, int ntiles,
+                                                 uint32_t *__restrict__ tot) {
+    __shared__ uint32_t sw[4];
+    uint32_t *c = cnt + (size_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const uint32_t x = b < ntiles ? c[b] : 0u;
+        uint32_t t;
+        const uint32_t inc = rs_block_scan(x, sw, &t);
+        if (b < ntiles) c[b] = carry + inc - x;
+        carry += t;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// stable scatter of one tile; LAST moves val[pos] instead of pos
+template <bool LAST>
+__global__ __launch_bounds__(256) void k_rs_scatter(
+    const uint32_t *__restrict__ key, const uint32_t *__restrict__ pos, long long n, int sh,
+    int ntiles, const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ tot,
+    uint32_t *__restrict__ key_out, uint32_t *__restrict__ pos_out,
+    const float2 *__restrict__ val, float2 *__restrict__ val_out) {
+    __shared__ uint32_t run[kRsDigits], wc[4][kRsDigits], sw[4];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const long long base = (long long)blockIdx.x * kRsTile;
+    uint32_t kk[kRsItems], pp[kRsItems];
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const long long i = base + it * 256 + tid;
+        kk[it] = i < n ? key[i] : 0u;
+        pp[it] = i < n ? pos[i] : 0u;
+    }
+    // run[d]: where this tile's next item of digit d goes
+    const uint32_t td = tot[tid];
+    uint32_t all;
+    const uint32_t inc = rs_block_scan(td, sw, &all);
+    run[tid] = inc - td + cnt[(size_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][tid] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const bool ok = base + it * 256 + tid < n;
+        const unsigned dg = (kk[it] >> sh) & 255u;
+        const uint64_t pm = rs_peers(dg, __ballot(ok));
+        const int r = rs_below(pm);
+        if (ok && r == 0) wc[w][dg] = (uint32_t)__popcll(pm);
+        __syncthreads();
+        if (ok) {
+            uint32_t o = run[dg] + (uint32_t)r;
+            for (int q = 0; q < w; ++q) o += wc[q][dg];
+            key_out[o] = kk[it];
+            if (LAST) val_out[o] = val[pp[it]];
+            else pos_out[o] = pp[it];
+        }
+        __syncthreads();
+        run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wc[q][tid] = 0u;
+        __syncthreads();
+    }
+}
+
 // Table gradient: one thread per run of equal sorted keys sums the run in
 // sorted (= contribution) order.
 __global__ __launch_bounds__(256) void k_hash_runs(const uint32_t *__restrict__ key,
-                                                   const uint32_t *__restrict__ pos,
                                                    const float2 *__restrict__ val, long long n,
                                                    float *__restrict__ grad) {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -299,14 +443,12 @@ __global__ __launch_bounds__(256) void k_hash_runs(const uint32_t *__restrict__ 
     // are ascending, so the run ends at the first different key
     float gx = 0.f, gy = 0.f;
     for (long long q = s; q < n; q += 8) {
-        uint32_t kq[8], pq[8];
+        uint32_t kq[8];
         float2 vq[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) kq[i] = q + i < n ? key[q + i] : kk + 1u;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) pq[i] = kq[i] == kk ? pos[q + i] : 0u;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) vq[i] = kq[i] == kk ? val[pq[i]] : make_float2(0.f, 0.f);
+        for (int i = 0; i < 8; ++i) vq[i] = kq[i] == kk ? val[q + i] : make_float2(0.f, 0.f);
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (kq[i] == kk) {
@@ -408,12 +550,34 @@ void hash_vjp(inrct_model *m, const float *theta, const int32_t *idx, long long 
     hipLaunchKernelGGL(k_hash_dw_sum, dim3((unsigned)cdiv(n_mlp, 256)), dim3(256), 0, s,
                        m->hash_part.as<float>(), ns, n_mlp, n_tab, grad);
     INRCT_CHECK_LAUNCH();
-    // table gradients: stable sort of the contributions by entry, run sums
-    size_t tb = m->hash_tmp.bytes;
-    INRCT_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(m->hash_tmp.ptr, tb, ckey, skey, cpos,
-                                                       spos, (int)nc, 0, m->hash_key_bits, s));
-    hipLaunchKernelGGL(k_hash_runs, dim3((unsigned)cdiv(nc, 256)), dim3(256), 0, s, skey, spos,
-                       cval, nc, grad);
+    // table gradients: stable sort of the contributions by entry (eight key
+    // bits a pass, ping-ponging between the two key / position buffers), run
+    // sums
+    const int ntiles = (int)cdiv(nc, kRsTile);
+    const int passes = (int)cdiv(m->hash_key_bits, 8);
+    uint32_t *cnt = m->hash_cnt.as<uint32_t>(), *tot = cnt + (size_t)kRsDigits * ntiles;
+    float2 *sval = m->hash_sval.as<float2>();
+    uint32_t *kin = ckey, *pin = cpos, *kout = skey, *pout = spos;
+    for (int p = 0; p < passes; ++p) {
+        const int sh = 8 * p;
+        hipLaunchKernelGGL(k_rs_count, dim3((unsigned)ntiles), dim3(256), 0, s, kin, nc, sh,
+                           ntiles, cnt);
+        INRCT_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_rs_scan, dim3((unsigned)kRsDigits), dim3(256), 0, s, cnt, ntiles,
+                           tot);
+        INRCT_CHECK_LAUNCH();
+        if (p + 1 < passes)
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)ntiles), dim3(256), 0, s, kin,
+                               pin, nc, sh, ntiles, cnt, tot, kout, pout, cval, sval);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)ntiles), dim3(256), 0, s, kin,
+                               pin, nc, sh, ntiles, cnt, tot, kout, pout, cval, sval);
+        INRCT_CHECK_LAUNCH();
+        std::swap(kin, kout);
+        std::swap(pin, pout);
+    }
+    hipLaunchKernelGGL(k_hash_runs, dim3((unsigned)cdiv(nc, 256)), dim3(256), 0, s, kin, sval,
+                       nc, grad);
     INRCT_CHECK_LAUNCH();
 }
 
@@ -447,14 +611,11 @@ void hash_setup(inrct_model *m, Arena &ar) {
     m->hash_skey.alloc(ar, sizeof(uint32_t) * nc);
     m->hash_spos.alloc(ar, sizeof(uint32_t) * nc);
     m->hash_val.alloc(ar, sizeof(float2) * nc);
+    m->hash_sval.alloc(ar, sizeof(float2) * nc);
     int bits = 1;
     while ((1LL << bits) < (long long)Lh * T) ++bits;
     m->hash_key_bits = bits;
-    size_t tb = 0;
-    INRCT_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint32_t *)nullptr,
-                                                       (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                       (uint32_t *)nullptr, (int)nc, 0, bits));
-    m->hash_tmp.alloc(ar, std::max<size_t>(tb, 256));
+    m->hash_cnt.alloc(ar, sizeof(uint32_t) * ((size_t)kRsDigits * cdiv(nc, kRsTile) + kRsDigits));
     const long long n_mlp = m->n_params - (long long)Lh * T * 2;
     m->hash_part.alloc(ar, sizeof(float) * (size_t)cdiv(kmax, kHashSlice) * n_mlp);
 }

@@ -53,12 +53,13 @@ struct inrct_model {
     int n_apart = 0;
 
     // hash encoding: level resolutions, per-point VJP rows, table-gradient
-    // contributions (keys, positions, sorted copies, values), sort scratch
-    // and dW slice partials
+    // contributions (keys, positions, the sort's second key / position
+    // buffers, values and sorted values), the sort's digit counts and dW
+    // slice partials
     int hash_res[inrct::kHashMaxLevels] = {0};
     int hash_row = 0, hash_key_bits = 0;
-    inrct::DevBuf hash_rows, hash_key, hash_pos, hash_skey, hash_spos, hash_val, hash_tmp,
-        hash_part;
+    inrct::DevBuf hash_rows, hash_key, hash_pos, hash_skey, hash_spos, hash_val, hash_sval,
+        hash_cnt, hash_part;
 
     bool bf16() const { return arch.mlp_dtype == INRCT_BF16; }
 };
