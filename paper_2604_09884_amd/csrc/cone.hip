@@ -519,9 +519,9 @@ __global__ __launch_bounds__(256, 4) void k_cone_fwd_lds(ConeDev g, const ConeTi
     int brow[kRows];
 #pragma unroll
     for (int r = 0; r < kRows; ++r) brow[r] = min(t.b0 + kRows * w + r, b1);
-    float acc[kRows];
+    float acc[kRows], acc_d[kRows];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
+    for (int r = 0; r < kRows; ++r) acc[r] = acc_d[r] = 0.f;
     const int lo = fov_only ? t.flo : t.slo, hi = fov_only ? t.fhi : t.shi;
     const int N = g.N;
     const int sfirst = (lo / kTileS) * kTileS;
@@ -549,7 +549,10 @@ __global__ __launch_bounds__(256, 4) void k_cone_fwd_lds(ConeDev g, const ConeTi
         zlo = f.zlo;
         __syncthreads();
         // Slice sl's taps are read (into buffer sl & 1) while slice sl - 1
-        // is integrated, so the LDS latency overlaps the arithmetic.
+        // is integrated, so the LDS latency overlaps the arithmetic.  The z
+        // weight stays the raw fraction (fx40_frac's numerator): a row sums
+        // the near taps (acc) and the weighted differences in units of 2^-32
+        // (acc_d), joined once at the end.
         constexpr int co = YPR ? 1 : kLdsOX, cz = YPR ? kLdsZY : kLdsZX;
         float v[2][kRows][4], fz[2][kRows], fo[2];
         auto fetch = [&](int sl, int bf) {
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(256, 4) void k_cone_fwd_lds(ConeDev g, const ConeTi
                 v[bf][r][1] = p[co];
                 v[bf][r][2] = p[cz];
                 v[bf][r][3] = p[cz + co];
-                fz[bf][r] = fx40_frac(Fz[r]);
+                fz[bf][r] = fx40_frac32(Fz[r]);
                 Fz[r] += dFz[r];
             }
             Fo += c.dFo;
@@ -578,7 +581,8 @@ __global__ __launch_bounds__(256, 4) void k_cone_fwd_lds(ConeDev g, const ConeTi
             for (int r = 0; r < kRows; ++r) {
                 const float t0 = fmaf(fo[bf], v[bf][r][1] - v[bf][r][0], v[bf][r][0]);
                 const float t1 = fmaf(fo[bf], v[bf][r][3] - v[bf][r][2], v[bf][r][2]);
-                acc[r] += fmaf(fz[bf][r], t1 - t0, t0);
+                acc[r] += t0;
+                acc_d[r] = fmaf(fz[bf][r], t1 - t0, acc_d[r]);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -587,7 +591,8 @@ __global__ __launch_bounds__(256, 4) void k_cone_fwd_lds(ConeDev g, const ConeTi
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const int b = t.b0 + kRows * w + r;
-        if (b <= b1) zout[((size_t)t.j * g.Nv + b) * g.Nu + a] = acc[r] * cone_step(g, c, b);
+        const float sum = fmaf(acc_d[r], 2.3283064365386963e-10f, acc[r]);
+        if (b <= b1) zout[((size_t)t.j * g.Nv + b) * g.Nu + a] = sum * cone_step(g, c, b);
     }
 }
 
