@@ -789,24 +789,41 @@ __device__ __forceinline__ void w2_column(const float *__restrict__ R, int rstri
     const float *rp = R + (b - blo) * rstride + a_local;
     // band jz = -1 .. ZC - 1: rows with floor(phi) = z0 + jz give (1 - w) to
     // voxel jz and w to voxel jz + 1.  The weights stay in units of 2^-32: w
-    // is fx40_frac's numerator, 1 - w is 2^32 minus that (each voxel's terms
-    // are summed as products, without cancellation); the power of two is in
-    // wo_s.
+    // is fx40_frac's numerator; the power of two is in wo_s.  Positions are
+    // taken relative to voxel z0 (the fractions are unchanged): row A of band
+    // jz lies in band jz and row B in band jz or jz + 1 (rows are 1/2 to 1
+    // voxel apart), so one compare of B's high word with (jz + 1) << 8 tells
+    // which.
+    ph -= (long long)z0 << 40;
+    // both rows of a band are read unconditionally (R holds the row after
+    // the last), so a band is straight-line code; the next band's rows are
+    // read before this band's arithmetic (their place depends on positions
+    // only), so the LDS latency overlaps it
+    float rA = rp[0], rB0 = rp[rstride];
 #pragma unroll
     for (int jz = -1; jz < ZC; ++jz) {
-        // both rows are read unconditionally (R holds the row after the
-        // last), so a band is straight-line code
-        const float rA = rp[0], rB0 = rp[rstride];
         const long long phB = ph + E1;
-        const bool inB = fx40_int(phB) == z0 + jz;
+        const bool inB = (int)(phB >> 32) < (jz + 1) * 256;
+        rp += inB ? 2 * rstride : rstride;
+        float nA = 0.f, nB0 = 0.f;
+        if (jz + 1 < ZC) {
+            nA = rp[0];
+            nB0 = rp[rstride];
+        }
+        // keep the reads above this band's arithmetic
+        __builtin_amdgcn_sched_barrier(0);
         const float rB = inB ? rB0 : 0.f;
         const float cA = fx40_frac32(ph), cB = fx40_frac32(phB);
         const float q = fmaf(cB, rB, cA * rA);
-        const float qn = fmaf(4294967296.f - cB, rB, (4294967296.f - cA) * rA);
+        // the lower voxel's share (2^32 - cA) rA + (2^32 - cB) rB, formed as
+        // 2^32 (rA + rB) - q: its rounding is within 2^-24 of the band's
+        // full-weight term
+        const float qn = fmaf(4294967296.f, rA + rB, -q);
         if (jz >= 0) acc[jz] = fmaf(qn, wo_s, acc[jz]);
         if (jz + 1 < ZC) acc[jz + 1] = fmaf(q, wo_s, acc[jz + 1]);
         ph = inB ? phB + E1 : phB;
-        rp += inB ? 2 * rstride : rstride;
+        rA = nA;
+        rB0 = nB0;
     }
 }
 
