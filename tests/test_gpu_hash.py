@@ -126,6 +126,36 @@ def test_hash_full_size_sampled():
     assert rel(g, g_ref) <= 1e-4
 
 
+def test_hash_full_size_table_gradient_at_full_k():
+    # |I| = n/16 = 12,868 points of the 512^2 hash workload: 823,552
+    # table-gradient contributions, sorted on 23-bit keys in three passes
+    # over 403 tiles; against the oracle, and bitwise repeatable
+    from paper_2604_09884_amd import ops
+    p = configs.C7
+    arch, N = p.arch, p.N
+    theta, _ = synth.random_theta(arch, 34)
+    fov = ogrid.fov_indices(2, N)
+    k = p.k()
+    m = ops.Model(arch, 2, N, "fp32", max_k=k)
+    th, Bd = dev(theta), dev(np.zeros(1))
+    cand = np.sort(np.random.default_rng(35).choice(fov, 2 * k, replace=False))
+    keep = _away_from_kinks(theta, arch, ogrid.coords(2, N, cand), 1e-4)
+    idx = cand[keep][:k]
+    assert idx.size == k
+    v = np.random.default_rng(36).standard_normal(k)
+    g = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(v), 16.0,
+                                    v_compact=True))
+    g2 = host(ops.inr_vjp_subsampled(m, th, Bd, dev(idx, torch.int32), dev(v), 16.0,
+                                     v_compact=True))
+    assert np.array_equal(g, g2)
+    g_ref = oinr.vjp(theta, None, ogrid.coords(2, N, idx), 16.0 * v, arch)
+    e = rel(g, g_ref)
+    et = rel(g[:arch.n_table], g_ref[:arch.n_table])
+    say("C7 full-k g rel", e, "table part", et)
+    report("fan2d-512-hash (C7)", "fp32", "g at |I| = 12,868", e, 1e-4)
+    assert e <= 1e-4 and et <= 1e-4
+
+
 def test_hash_single_point_and_all_hashed_levels():
     # k = 1, and a 3D model whose every level is hashed (T = 2^6 < (N_0+1)^3)
     from paper_2604_09884_amd import ops
