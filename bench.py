@@ -106,12 +106,15 @@ def cpu_baseline(p, target_s):
             break
         S = min(2 * S, n)
     per_E = t_e / S * n
-    # P and P^T on R rays of view 0
+    # P and P^T on R rays drawn from four random views (and, in 3-D, eight
+    # random detector rows of them)
+    views = np.sort(rng.choice(p.n_views, size=min(4, p.n_views), replace=False))
     if p.dim == 3:
+        rows = np.sort(rng.choice(p.n_v, size=min(8, p.n_v), replace=False))
         p0, d = ogeo.cone3d_rays(p.n_views, p.n_u, p.n_v, p.du, p.dv, p.dso, p.dod,
-                                 views=[0], rows=np.arange(p.n_v // 2 - 1, p.n_v // 2 + 1))
+                                 p.view_span, views=views, rows=rows)
     else:
-        p0, d = ogeo.problem_rays(p, views=[0])
+        p0, d = ogeo.problem_rays(p, views=views)
     R = min(1024, p0.shape[0])
     sel = rng.choice(p0.shape[0], size=R, replace=False)
     t0 = time.perf_counter()
@@ -142,10 +145,11 @@ def cpu_baseline(p, target_s):
     return {
         "value": 1.0 / total, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
         "sample": ("FP64 oracle on a bounded sample scaled to one full step: E on %d FOV "
-                   "points (x%.0f), P and P^T on %d rays (x%.0f), VJP on %d samples "
+                   "points (x%.0f), P and P^T on %d rays of 4 random views%s (x%.0f), VJP on %d samples "
                    "(x%.0f), sampler on %d draws, Adam on all %d parameters; "
                    "est. %.1f s per step (E %.1f s, P %.1f s, P^T %.1f s, VJP %.1f s)"
-                   % (S, n / S, R, m / R, Q, k / Q, D, theta.size, total, per_E, per_P,
+                   % (S, n / S, R, " and 8 random rows" if p.dim == 3 else "", m / R, Q,
+                      k / Q, D, theta.size, total, per_E, per_P,
                       per_PT, per_V)),
         "host_cpus": os.cpu_count(),
     }
