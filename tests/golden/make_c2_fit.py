@@ -8,11 +8,13 @@ Calls only the oracle and the seeded input generators; nothing here comes
 from the GPU path.  Most of a step is the image evaluation E (the SIREN over
 all 206k FOV pixels); with --threads T the oracle's own forward pass runs on T
 chunks of the pixel list at once (rows are independent, so only the BLAS
-blocking changes).  With eight threads a step takes a few seconds, the whole
-fit a few hours; single-threaded about 15-20 s a step:
+blocking changes).  On seven threads of an 8-core host a step takes about
+3.5 s and the fit about two hours; single-threaded about 15-20 s a step.  The
+committed record was written by
 
-    OPENBLAS_NUM_THREADS=1 python tests/golden/make_c2_fit.py --threads 8 \
-        [--steps 2000] [--every 20] [--out PATH]
+    OPENBLAS_NUM_THREADS=1 python tests/golden/make_c2_fit.py --threads 7
+
+(defaults: --steps 2000 --every 20, written next to this script).
 """
 import argparse
 import concurrent.futures as cf
