@@ -381,6 +381,89 @@ __global__ __launch_bounds__(256) void k_ramp(const float *__restrict__ q, float
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// The same filter, register-tiled: a thread computes B consecutive outputs
+// a0 .. a0 + B - 1 of a row (B odd, so the lanes' LDS addresses, B words
+// apart, fall in distinct banks).  At odd offset j the outputs need the inputs
+// at a - j and a + j: two windows of B values, which move by two values at
+// the next odd offset.  The windows are circular register buffers whose
+// rotation is fixed at compile time (B taps per unrolled group), so a tap
+// reads four new values from LDS for 2B operations instead of three for two.
+// Each output adds its terms in k_ramp's order (the same float result).  A
+// workgroup holds `rpb` rows at once, `tpr` threads each.
+constexpr int kRampPad = 16;  // zero floats before and after a staged row (>= B)
+
+template <int B>
+__global__ __launch_bounds__(256) void k_ramp_tiled(const float *__restrict__ q,
+                                                    float *__restrict__ r, int nu, int64_t rows,
+                                                    int tpr, int rpb, double du,
+                                                    double *__restrict__ partials) {
+    extern __shared__ float lds[];
+    const int nt = nu / 2;  // odd offsets 1, 3, ..., < nu
+    const int stride = 3 * nu + 2 * kRampPad;
+    float *tap = lds;                // [nt]: f_{2i+1}
+    float *rowbuf = lds + nt;        // rpb x [pad, nu zeros, the row, nu zeros, pad]
+    __shared__ double sh[256];
+    const float f0 = (float)(1.0 / (4.0 * du));
+    const float cf = (float)(-1.0 / (M_PI * M_PI * du));
+    for (int i = threadIdx.x; i < nt; i += 256) {
+        const int jj = 2 * i + 1;
+        tap[i] = cf / ((float)jj * (float)jj);
+    }
+    for (int i = threadIdx.x; i < rpb * stride; i += 256) rowbuf[i] = 0.f;
+    const int grp = threadIdx.x / tpr, t = threadIdx.x - grp * tpr;
+    const int a0 = t * B;
+    const bool mine = grp < rpb;
+    const float *c = rowbuf + (mine ? grp : 0) * stride + kRampPad + nu;  // c[0]: the row's first value
+    double acc = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * rpb; base < rows;
+         base += (int64_t)gridDim.x * rpb) {
+        const int64_t rw = base + grp;
+        const bool live = mine && rw < rows;
+        __syncthreads();  // the previous rows' reads are done
+        if (live) {
+            float *dst = rowbuf + grp * stride + kRampPad + nu;
+            for (int i = t; i < nu; i += tpr) dst[i] = q[rw * nu + i];
+        }
+        __syncthreads();
+        if (!live || a0 >= nu) continue;
+        float sum[B], L[B], R[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            sum[b] = f0 * c[a0 + b];
+            L[b] = c[a0 + b - 1];
+            R[b] = c[a0 + b + 1];
+        }
+        // at step u of a group, L[b] (the input at a0 + b - j) sits in slot
+        // (b - 2u) mod B and R[b] (at a0 + b + j) in slot (b + 2u) mod B
+        for (int i0 = 0; i0 < nt; i0 += B) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = i0 + u;
+                if (i < nt) {
+                    const int jj = 2 * i + 1;
+                    const float tp = tap[i];
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        sum[b] += tp * (L[((b - 2 * u) % B + B) % B] + R[(b + 2 * u) % B]);
+                    // the next offset's new values: L[0], L[1] and R[B-2], R[B-1]
+                    L[((-2 * (u + 1)) % B + B) % B] = c[a0 - jj - 2];
+                    L[((1 - 2 * (u + 1)) % B + B) % B] = c[a0 - jj - 1];
+                    R[(2 * u) % B] = c[a0 + B + jj];
+                    R[(2 * u + 1) % B] = c[a0 + B + 1 + jj];
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (a0 + b < nu) {
+                r[rw * nu + a0 + b] = sum[b];
+                acc += 0.5 * (double)c[a0 + b] * (double)sum[b];
+            }
+    }
+    const double tot = block_sum_f64(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
 }  // namespace inrct
 
 // ==================================================================== ABI
@@ -469,8 +552,28 @@ void residual_loss(inrct_geom *geom, int loss, const float *z, const float *y,
                            q, m);
         INRCT_CHECK_LAUNCH();
         const int nu = geom->g.n_u;
-        hipLaunchKernelGGL(k_ramp, dim3(nb), dim3(256), sizeof(float) * (3 * nu + nu / 2), s, q,
-                           r, nu, m / nu, geom->g.du, part);
+        // the register-tiled filter: B outputs a thread (7, or more for wide
+        // detectors), whole waves a row, as many rows a workgroup as fit
+        int B = 7;
+        while (B <= 13 && cdiv(nu, B) > 256) B += 2;
+        if (B <= 13) {
+            const int tpr = (int)(cdiv(cdiv(nu, B), 64) * 64);
+            const int rpb = 256 / tpr;
+            const size_t lds = sizeof(float) * ((size_t)(nu / 2) +
+                                                (size_t)rpb * (3 * nu + 2 * kRampPad));
+            const int64_t rows = m / nu;
+#define RAMP_TILED(B_)                                                                    \
+    hipLaunchKernelGGL(k_ramp_tiled<B_>, dim3(nb), dim3(256), lds, s, q, r, nu, rows, tpr, \
+                       rpb, geom->g.du, part)
+            if (B == 7) RAMP_TILED(7);
+            else if (B == 9) RAMP_TILED(9);
+            else if (B == 11) RAMP_TILED(11);
+            else RAMP_TILED(13);
+#undef RAMP_TILED
+        } else {
+            hipLaunchKernelGGL(k_ramp, dim3(nb), dim3(256), sizeof(float) * (3 * nu + nu / 2),
+                               s, q, r, nu, m / nu, geom->g.du, part);
+        }
         INRCT_CHECK_LAUNCH();
     }
     if (loss_out) launch_sum_partials(part, nb, loss_out, s);

@@ -111,6 +111,36 @@ def test_residual_ls_and_fls():
     assert abs(host(lo) - oloss.fls_loss(zz, yy, p.du)) <= 1e-5 * abs(oloss.fls_loss(zz, yy, p.du))
 
 
+# detector widths that reach every layout of the register-tiled ramp filter
+# (four, two and one rows a workgroup; 7 and 9 outputs a thread) and, past
+# 3328 bins, the direct filter
+FLS_CASES = [
+    ("par2d-725", configs.par2d_problem(512, 9, 725)),
+    ("cone3d-768", configs.cone_problem(64, 2, 768)),
+    ("par2d-1000", configs.par2d_problem(512, 5, 1000)),
+    ("par2d-2001", configs.par2d_problem(1024, 3, 2001)),
+    ("par2d-3400", configs.par2d_problem(1024, 2, 3400)),
+]
+
+
+@pytest.mark.parametrize("name,p", FLS_CASES, ids=[c[0] for c in FLS_CASES])
+def test_fls_residual_detector_widths(name, p):
+    ops = _ops()
+    g = ops.Geometry(p)
+    z = RNG(6).standard_normal(g.n_rays).astype(np.float32)
+    y = RNG(7).standard_normal(g.n_rays).astype(np.float32)
+    zz, yy = z.reshape(g.proj_shape), y.reshape(g.proj_shape)
+    r, lo = ops.residual_loss(g, dev(z), dev(y), 1)
+    ref = oloss.fls_residual(zz, yy, p.du)
+    L_ref = oloss.fls_loss(zz, yy, p.du)
+    e = rel(host(r), ref)
+    say("FLS %s: rows %d x %d bins, r rel %.3e, loss rel %.3e"
+        % (name, g.n_rays // p.n_u, p.n_u, e, abs(host(lo) - L_ref) / abs(L_ref)))
+    report(name, "fp32", "FLS residual F(z - y)", e, 1e-5)
+    assert e <= 1e-5
+    assert abs(host(lo) - L_ref) <= 1e-5 * abs(L_ref)
+
+
 ARCHS = [
     ("ffn2d-128", configs.C1.arch, configs.par2d_problem(45, 20, 67)),
     ("siren2d-256", configs.C2.arch, configs.par2d_problem(41, 20, 61)),
