@@ -131,6 +131,61 @@ __device__ __forceinline__ void hash_forward(const HashDev &h, int ix, int iy, i
     }
 }
 
+// f_theta at one grid point, for E: hash_forward's arithmetic in its order,
+// with the last hidden layer fused with the output (each unit's activation
+// goes into f as soon as it is formed, in unit order) and that layer's unit
+// loop kept rolled, so only one layer of activations is held in registers.
+template <int W, int LMAX, int DIM>
+__device__ __forceinline__ float hash_eval_point(const HashDev &h, int ix, int iy, int iz) {
+    const float *W1 = h.theta + h.loff[1];
+    float a[W];
+    {
+        float z[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) z[i] = W1[(size_t)W * h.K + i];
+        for (int l = 0; l < h.levels; ++l) {
+            const float2 e = hash_level<DIM>(h, l, ix, iy, iz, nullptr, nullptr);
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+                z[i] += W1[(size_t)i * h.K + 2 * l] * e.x + W1[(size_t)i * h.K + 2 * l + 1] * e.y;
+        }
+#pragma unroll
+        for (int i = 0; i < W; ++i) a[i] = fmaxf(z[i], 0.f);
+    }
+    const float *Wo = h.theta + h.loff[h.L + 1];
+    float f = Wo[W];
+    if (h.L == 1) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) f += Wo[j] * a[j];
+        return f;
+    }
+#pragma unroll
+    for (int l = 1; l < LMAX; ++l) {
+        const float *Wl = h.theta + h.loff[l + 1];
+        if (l == h.L - 1) {
+#pragma unroll 1
+            for (int i = 0; i < W; ++i) {
+                float s = Wl[W * W + i];
+#pragma unroll
+                for (int j = 0; j < W; ++j) s += Wl[i * W + j] * a[j];
+                f += Wo[i] * fmaxf(s, 0.f);
+            }
+            break;
+        }
+        float b[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            float s = Wl[W * W + i];
+#pragma unroll
+            for (int j = 0; j < W; ++j) s += Wl[i * W + j] * a[j];
+            b[i] = fmaxf(s, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < W; ++i) a[i] = b[i];
+    }
+    return f;
+}
+
 template <int W, int LMAX, int DIM>
 __global__ __launch_bounds__(256) void k_hash_eval(HashDev h, long long n, int mode,
                                                    const int32_t *__restrict__ idx,
@@ -140,30 +195,21 @@ __global__ __launch_bounds__(256) void k_hash_eval(HashDev h, long long n, int m
     int ix, iy, iz;
     long long g;
     hash_point(h, q, mode, idx, &ix, &iy, &iz, &g);
-    float acts[LMAX][W];
-    hash_forward<W, LMAX, DIM>(h, ix, iy, iz, acts, nullptr);
-    const float *Wo = h.theta + h.loff[h.L + 1];
-    float f = Wo[W];
-    for (int l = 0; l < LMAX; ++l)
-        if (l == h.L - 1) {
-#pragma unroll
-            for (int j = 0; j < W; ++j) f += Wo[j] * acts[l][j];
-        }
-    out[mode == 0 ? g : q] = f;
+    out[mode == 0 ? g : q] = hash_eval_point<W, LMAX, DIM>(h, ix, iy, iz);
 }
 
 // Row of point t (R floats): a_0 (K) | a_1..a_L (W each) | d_1..d_L (W each)
 // | d_out.  Contributions of point t: (level, vertex) keys and the two
 // weighted feature gradients.
 template <int W, int LMAX, int DIM>
-__global__ __launch_bounds__(256) void k_hash_vjp(HashDev h, const int32_t *__restrict__ idx,
+__global__ __launch_bounds__(64) void k_hash_vjp(HashDev h, const int32_t *__restrict__ idx,
                                                   long long k, const float *__restrict__ v,
                                                   int v_compact, float scale,
                                                   float *__restrict__ rows, int R,
                                                   uint32_t *__restrict__ ckey,
                                                   uint32_t *__restrict__ cpos,
                                                   float2 *__restrict__ cval) {
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long t = (long long)blockIdx.x * 64 + threadIdx.x;
     if (t >= k) return;
     int ix, iy, iz;
     long long g;
@@ -514,7 +560,7 @@ template <int W, int LM, int DIM>
 static void launch_hash_vjp(const HashDev &h, const int32_t *idx, long long k, const float *v,
                             int v_compact, float scale, float *rows, int R, uint32_t *ckey,
                             uint32_t *cpos, float2 *cval, hipStream_t s) {
-    hipLaunchKernelGGL((k_hash_vjp<W, LM, DIM>), dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, h,
+    hipLaunchKernelGGL((k_hash_vjp<W, LM, DIM>), dim3((unsigned)cdiv(k, 64)), dim3(64), 0, s, h,
                        idx, k, v, v_compact, scale, rows, R, ckey, cpos, cval);
 }
 
