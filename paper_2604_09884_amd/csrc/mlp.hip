@@ -1890,6 +1890,13 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
         const int nchunks = (int)((m->nfrag_h + m->nfrag_vb) / 32);
         hipLaunchKernelGGL(k_vjp_w, dim3((unsigned)grid), dim3(512), 0, s, d, idx, k, j0, v,
                            v_compact, scale, ntiles, nchunks, (const char *)m->frag_v.ptr, o);
+    } else if (BF && W == 128 && ACT == INRCT_FFN) {
+        // two column tiles a wave: every weight fragment read feeds two products
+        constexpr int NT2 = 2;
+        const long long per_block = 4LL * 32 * NT2;
+        hipLaunchKernelGGL((k_vjp_tile<W, NT2, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
+                           dim3(256), 0, s, d, idx, k, j0, v, v_compact, scale, ncols, sink,
+                           m->dlt.as<St>(), dlt_L1);
     } else {
         const long long per_block = 4LL * 32 * NT;
         hipLaunchKernelGGL((k_vjp_tile<W, NT, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
