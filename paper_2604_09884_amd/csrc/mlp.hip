@@ -1538,16 +1538,25 @@ struct GemmTile2 {
     long long act_off;    // element offset of a_{l-1} rows
     long long theta_off;  // parameter offset of layer l (W then b)
     int M, R, tn, bias;   // rows, inputs, first column, sums the bias gradient
+    int tw;               // columns the tile covers (its width: 256 or 128)
 };
 constexpr int kDwPart = 256 * 256 + 256;  // partial floats per (tile, slice)
-constexpr int kDwSlot = 32 * 1024;        // one group: 32 fragments of 1 KB
 
+// dW = delta A^T for one tile of TILE x TILE (256, or 128 for width-128
+// MLPs, whose layers a 256-wide tile would cover a quarter of) over one
+// slice of points.  Four waves, each (TILE / 64)^2 products of 32 x 32;
+// partials are stored in the 256-stride layout either way.
+template <int TILE>
 __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ tiles,
                                                   const __bf16 *__restrict__ dlt,
                                                   const __bf16 *__restrict__ act, long long P,
                                                   long long ncols, int kslice, int accumulate,
                                                   float *__restrict__ part, int ntiles) {
-    __shared__ __attribute__((aligned(16))) char ring[4 * kDwSlot];
+    constexpr int MA = TILE / 64;        // 32-row (and 32-column) blocks per wave
+    constexpr int FG = TILE / 8;         // fragments per group of 32 points
+    constexpr int NC = FG / 4;           // copies per wave per group
+    constexpr int SLOT = FG * 1024;
+    __shared__ __attribute__((aligned(16))) char ring[4 * SLOT];
     const GemmTile2 T = tiles[blockIdx.x];
     const int ks = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -1558,24 +1567,28 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
     long long p1 = p0 + kslice;
     if (p1 > ncols) p1 = ncols;
     const int G = p1 > p0 ? (int)((p1 - p0) / 32) : 0;
-    f32x16 acc[4][4];
+    f32x16 acc[MA][MA];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < MA; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (f32x16){0};
-    float bs[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < MA; ++b) acc[a][b] = (f32x16){0};
+    float bs[MA];
+#pragma unroll
+    for (int a = 0; a < MA; ++a) bs[a] = 0.f;
     const bool dob = T.bias && wn == 0;
     if (G > 0) {
-        // fragment f of a group (lane l: row 32 (f / 2 % 8) + l % 32, points
-        // 16 (f % 2) + 8 (l / 32) .. + 7): f < 16 delta rows, f >= 16
-        // activation rows of this tile's columns.  Rows past the layer read
-        // its last row (their products are never summed into a gradient).
-        const __bf16 *src[8];
+        // fragment f of a group (lane l: row 32 (f / 2 % (TILE / 32)) + l % 32,
+        // points 16 (f % 2) + 8 (l / 32) .. + 7): f < FG / 2 delta rows,
+        // f >= FG / 2 activation rows of this tile's columns.  Rows past the
+        // layer read its last row (their products are never summed into a
+        // gradient).
+        const __bf16 *src[NC];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int f = 8 * wave + q;
-            const int row = 32 * ((f >> 1) & 7) + i, off = 16 * (f & 1) + 8 * h;
-            if (f < 16) src[q] = dlt + T.dlt_off + (long long)min(row, T.M - 1) * P + p0 + off;
+        for (int q = 0; q < NC; ++q) {
+            const int f = NC * wave + q;
+            const int fr = f < FG / 2 ? f : f - FG / 2;
+            const int row = 32 * ((fr >> 1) % (TILE / 32)) + i, off = 16 * (fr & 1) + 8 * h;
+            if (f < FG / 2) src[q] = dlt + T.dlt_off + (long long)min(row, T.M - 1) * P + p0 + off;
             else src[q] = act + T.act_off + (long long)min(T.tn + row, T.R - 1) * P + p0 + off;
         }
         const unsigned lds0 = __builtin_amdgcn_readfirstlane(
@@ -1585,10 +1598,10 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
         auto issue = [&](int g, int slot) {
             const long long dp = 32LL * (g < G ? g : G - 1);
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
+            for (int q = 0; q < NC; ++q)
                 asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
                              :
-                             : "s"(lds0 + (unsigned)(slot * kDwSlot + (8 * wave + q) * 1024)),
+                             : "s"(lds0 + (unsigned)(slot * SLOT + (NC * wave + q) * 1024)),
                                "v"(src[q] + dp)
                              : "memory", "m0");
         };
@@ -1598,21 +1611,22 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
         for (int g = 0; g < G; ++g) {
             // this wave's copies of group g have landed (those of g + 1 and
             // g + 2 may be in flight); the barrier publishes every wave's
-            asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+            if constexpr (NC == 8) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+            else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
             __syncthreads();
             // the slot read through an address the compiler cannot trace, so
             // no read is hoisted above the wait and barrier
             unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) char *)ring +
-                           (unsigned)((g & 3) * kDwSlot) + lane * 16;
+                           (unsigned)((g & 3) * SLOT) + lane * 16;
             asm volatile("" : "+v"(off));
             const bf16x8 *F = (const bf16x8 *)(__attribute__((address_space(3))) const bf16x8 *)(size_t)off;
-            bf16x8 A[2][4], B[2][4];
+            bf16x8 A[2][MA], B[2][MA];
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    A[j][a] = F[(((wm * 4 + a) << 1) | j) * 64];
-                    B[j][a] = F[(16 + (((wn * 4 + a) << 1) | j)) * 64];
+                for (int a = 0; a < MA; ++a) {
+                    A[j][a] = F[(((wm * MA + a) << 1) | j) * 64];
+                    B[j][a] = F[(FG / 2 + (((wn * MA + a) << 1) | j)) * 64];
                 }
             // the slot of group g - 1 is free (every wave passed this
             // barrier): group g + 3 goes there
@@ -1620,14 +1634,14 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < MA; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
+                    for (int b = 0; b < MA; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[j][a], B[j][b],
                                                                             acc[a][b], 0, 0, 0);
             if (dob) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < MA; ++a)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -1639,11 +1653,11 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
     }
     float *__restrict__ out = part + ((long long)ks * ntiles + blockIdx.x) * kDwPart;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < MA; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < MA; ++b) {
             // rows crow(r, h) = 8 (r / 4) + 4 h + r % 4 of the 32-row tile
-            float *o = out + (wm * 128 + 32 * a + 4 * h) * 256 + wn * 128 + 32 * b + i;
+            float *o = out + (wm * (TILE / 2) + 32 * a + 4 * h) * 256 + wn * (TILE / 2) + 32 * b + i;
             if (accumulate) {
                 // all sixteen earlier partials in flight before any store
                 float prev[16];
@@ -1657,10 +1671,10 @@ __global__ __launch_bounds__(256) void k_dw_gemm2(const GemmTile2 *__restrict__ 
         }
     if (dob) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a < MA; ++a) {
             const float t = bs[a] + __shfl_xor(bs[a], 32);
             if (h == 0) {
-                float *o = out + 256 * 256 + wm * 128 + 32 * a + i;
+                float *o = out + 256 * 256 + wm * (TILE / 2) + 32 * a + i;
                 *o = accumulate ? *o + t : t;
             }
         }
@@ -1678,7 +1692,7 @@ __global__ void k_dw_reduce2(const GemmTile2 *__restrict__ tiles, const float *_
     long long dst;
     if (e < 256 * 256) {
         const int row = e / 256, col = T.tn + e % 256;
-        if (row >= T.M || col >= T.R) return;
+        if (row >= T.M || col >= T.R || e % 256 >= T.tw) return;
         dst = T.theta_off + (long long)row * T.R + col;
     } else {
         const int row = e - 256 * 256;
@@ -1905,10 +1919,16 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
     }
     INRCT_CHECK_LAUNCH();
     if constexpr (BF)
-        hipLaunchKernelGGL(k_dw_gemm2, dim3(m->ntiles, m->nks), dim3(256), 0, s,
-                           m->tiles.as<GemmTile2>(), (const __bf16 *)m->dlt.ptr,
-                           (const __bf16 *)m->act.ptr, P, ncols, m->kslice, accumulate,
-                           m->part.as<float>(), m->ntiles);
+        if (m->dw_tile == 128)
+            hipLaunchKernelGGL(k_dw_gemm2<128>, dim3(m->ntiles, m->nks), dim3(256), 0, s,
+                               m->tiles.as<GemmTile2>(), (const __bf16 *)m->dlt.ptr,
+                               (const __bf16 *)m->act.ptr, P, ncols, m->kslice, accumulate,
+                               m->part.as<float>(), m->ntiles);
+        else
+            hipLaunchKernelGGL(k_dw_gemm2<256>, dim3(m->ntiles, m->nks), dim3(256), 0, s,
+                               m->tiles.as<GemmTile2>(), (const __bf16 *)m->dlt.ptr,
+                               (const __bf16 *)m->act.ptr, P, ncols, m->kslice, accumulate,
+                               m->part.as<float>(), m->ntiles);
     else
         hipLaunchKernelGGL((k_dw_gemm<BF>), dim3(m->ntiles, m->nks), dim3(256), 0, s,
                            m->tiles.as<GemmTile>(), (const St *)m->dlt.ptr, (const St *)m->act.ptr,
@@ -2128,7 +2148,9 @@ void build_model(inrct_model *m, Arena &ar) {
         m->sig.alloc(ar, m->sig_elems * sizeof(float));
     }
     if (bf) {
-        // full-width dW tiles: layer l = 1..L+1, 256 input columns each
+        // full-width dW tiles: layer l = 1..L+1, dw_tile input columns each
+        // (128 for width-128 MLPs, whose layers fit one 128 x 128 tile)
+        m->dw_tile = W <= 128 ? 128 : 256;
         std::vector<GemmTile2> tiles2;
         for (int l = 1; l <= L + 1; ++l) {
             GemmTile2 t{};
@@ -2137,7 +2159,8 @@ void build_model(inrct_model *m, Arena &ar) {
             t.dlt_off = (long long)(l - 1) * W * P;
             t.act_off = m->act_off[l - 1];
             t.theta_off = m->loff[l];
-            for (int tn = 0; tn < t.R; tn += 256) {
+            t.tw = m->dw_tile;
+            for (int tn = 0; tn < t.R; tn += m->dw_tile) {
                 GemmTile2 u = t;
                 u.tn = tn;
                 u.bias = tn == 0;

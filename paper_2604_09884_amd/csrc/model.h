@@ -43,6 +43,7 @@ struct inrct_model {
     long long act_elems = 0, dlt_elems = 0, sig_elems = 0;
     inrct::DevBuf act, dlt, sig, part, tiles, mask;
     int ntiles = 0;
+    int dw_tile = 256;           // BF16 dW tile width (128 for width-128 MLPs)
 
     // sampler: FOV-rank membership bytes and per-block counts
     inrct::DevBuf flags, blk;

@@ -114,6 +114,41 @@ def test_vjp_bf16_width256_across_chunks():
     assert et <= 2e-2
 
 
+def test_vjp_bf16_width128_across_chunks():
+    # the BF16 width-128 FFN of the serving mix's 3D requests (64 frequencies,
+    # 3 x 128): two column tiles a wave in the recompute, and the 128 x 128
+    # dW tiles with their split-K partials accumulated over three chunks
+    from paper_2604_09884_amd import configs as cfg
+    ops = _ops()
+    arch = cfg.serving_mix(64)[1].arch
+    assert arch.kind == "ffn" and arch.width == 128
+    N = 96
+    fov = ogrid.fov_indices(3, N)
+    theta, B = synth.random_theta(arch, 37)
+    idx = np.sort(RNG(38).choice(fov, size=2 * CHUNK + 4321, replace=False))
+    k = idx.size
+    X = ogrid.coords(3, N, idx)
+    v = _smooth_field(X, 39)
+    m = ops.Model(arch, 3, N, "bf16", max_k=k)
+    g = host(ops.inr_vjp_subsampled(m, dev(theta), dev(B.ravel()), dev(idx, torch.int32),
+                                    dev(v), 1.5, v_compact=True))
+    g_ref = _oracle_vjp(theta, B, X, 1.5 * v, arch)
+    e = rel(g, g_ref)
+    say("bf16 width-128 g rel over %d chunks (k %d)" % (-(-k // CHUNK), k), e)
+    report("ffn 3->128+3x128, %d points (3 chunks)" % k, "bf16", "g (VJP)", e, 2e-2)
+    assert e <= 2e-2
+    # every layer's weight and bias blocks on their own (a dW tile that
+    # missed a block of rows or columns would show here)
+    off = arch.n_table
+    for fi, fo in arch.layer_dims():
+        for n in (fi * fo, fo):
+            eb = rel(g[off:off + n], g_ref[off:off + n])
+            say("  block of %d: rel %.3e" % (n, eb))
+            assert eb <= 5e-2
+            off += n
+    assert off == g.size
+
+
 def test_vjp_at_the_501_cube_index_set():
     # the 987,757-point I the 501^3 step draws at step 0 (four chunks),
     # with a smooth cotangent and the step's scale n/k, BF16 as benchmarked
