@@ -1315,14 +1315,14 @@ __global__ __launch_bounds__(512) void k_vjp_w(MlpDev m, const int32_t *__restri
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// The width-128 BF16 FFN variant is held to two waves per SIMD (its fragment
+// reads otherwise take every register, leaving one wave per SIMD).
 template <int W, int NT, bool BF, int ACT>
-__global__ __launch_bounds__(256) void k_vjp_tile(MlpDev m, const int32_t *__restrict__ idx,
-                                                  long long k, long long j0,
-                                                  const float *__restrict__ v, int v_compact,
-                                                  float scale, long long ncols,
-                                                  ActSink<BF> sink,
-                                                  typename Prec<BF>::Store *__restrict__ dlt,
-                                                  long long dlt_off_L1) {
+__global__ __launch_bounds__(256, (W <= 128 && NT == 1 && BF && ACT == INRCT_FFN) ? 2 : 1)
+void k_vjp_tile(MlpDev m, const int32_t *__restrict__ idx, long long k, long long j0,
+                const float *__restrict__ v, int v_compact, float scale, long long ncols,
+                ActSink<BF> sink, typename Prec<BF>::Store *__restrict__ dlt,
+                long long dlt_off_L1) {
     typedef Prec<BF> PR;
     typedef typename PR::Op Op;
     typedef typename PR::Store St;
@@ -1904,13 +1904,6 @@ static void launch_vjp_chunk(inrct_model *m, const MlpDev &d, const int32_t *idx
         const int nchunks = (int)((m->nfrag_h + m->nfrag_vb) / 32);
         hipLaunchKernelGGL(k_vjp_w, dim3((unsigned)grid), dim3(512), 0, s, d, idx, k, j0, v,
                            v_compact, scale, ntiles, nchunks, (const char *)m->frag_v.ptr, o);
-    } else if (BF && W == 128 && ACT == INRCT_FFN) {
-        // two column tiles a wave: every weight fragment read feeds two products
-        constexpr int NT2 = 2;
-        const long long per_block = 4LL * 32 * NT2;
-        hipLaunchKernelGGL((k_vjp_tile<W, NT2, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
-                           dim3(256), 0, s, d, idx, k, j0, v, v_compact, scale, ncols, sink,
-                           m->dlt.as<St>(), dlt_L1);
     } else {
         const long long per_block = 4LL * 32 * NT;
         hipLaunchKernelGGL((k_vjp_tile<W, NT, BF, ACT>), dim3((unsigned)cdiv(ncols, per_block)),
